@@ -1,0 +1,190 @@
+/*
+ * hamsim.h -- C ABI of the MI355X (gfx950) library for diagonal-budgeted
+ * Trotterized Hamiltonian simulation.
+ *
+ * The paper's problem statement (Section 3.4): given a Hermitian H, a total
+ * time t and an initial state x, approximate e^{-iHt} x without dense
+ * matrices.  H arrives as a sum of Pauli strings with coefficients
+ * (Section 4.4, "Benchmarks").  The library splits H into factors (the H_j of
+ * the Trotter product, Eq. 4), exponentiates each factor exactly, stores each
+ * factor exponential in the diagonal layout of Eq. 6 (Section 3.2), and
+ * evolves the state by one DIA SpMV per factor per step (Alg. 1 inside the
+ * repeat loop of Alg. 3).
+ *
+ * Conventions
+ *  - A Pauli string has n_qubits characters from "IXYZ"; character k acts on
+ *    qubit k, which is bit k of the basis index (least-significant first).
+ *  - A state is N = 2^n_qubits complex amplitudes, interleaved (re, im), in
+ *    the factors' dtype: HS_C64 = 2 x float, HS_C128 = 2 x double.  A batch
+ *    of B states is B contiguous states ([B][N]).
+ *  - Diagonal d of an N x N operator holds A[r, r+d] at storage index
+ *    min(r, r+d) and has N - |d| entries (Section 3.2, Eq. 6; element map of
+ *    the DiagonalTimesVector schematic, Section 3.3).
+ *  - Device pointers are HIP device addresses on the current device; a
+ *    stream argument is a hipStream_t (NULL = the default stream).  All device
+ *    work is enqueued on that stream.
+ *  - Every function returns an hs_status.  On failure nothing is left half
+ *    built, output handles are set to NULL, and hs_last_error() returns a
+ *    message for the calling thread.  No C++ exception crosses this ABI.
+ *  - Distinct hs_factors handles may be used concurrently from different
+ *    threads on different streams; one handle must not be evolved
+ *    concurrently with itself.
+ */
+#ifndef HAMSIM_H
+#define HAMSIM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hs_factors_s *hs_factors;
+
+typedef enum { HS_C64 = 0, HS_C128 = 1 } hs_dtype;
+
+typedef enum {
+    HS_OK = 0,
+    HS_EINVAL = 1,          /* bad argument (size, pointer, string, flag) */
+    HS_ENONHERMITIAN = 2,   /* a coefficient has |Im c| > 1e-12 max|c| */
+    HS_EBUDGET = 3,         /* a single term's exponential exceeds the budget */
+    HS_ENOMEM = 4,          /* device allocation failed */
+    HS_EDEVICE = 5,         /* a HIP call failed */
+    HS_ETOOLARGE = 6        /* n_qubits > 30, or a factor support > 10 qubits */
+} hs_status;
+
+/* build flags */
+#define HS_MERGE_DIAG 1u    /* fold the diagonal factor D into the first group (U_1 D); default in Python */
+/* evolve flags */
+#define HS_RENORM 2u        /* divide each state by its FP64 norm after every step */
+#define HS_NO_FUSE 4u       /* one launch per factor instead of fused multi-factor tiles */
+
+#define HS_MAX_QUBITS 30
+#define HS_MAX_SUPPORT 10
+#define HS_MAX_BATCH 8      /* states per launch; larger batches run in chunks */
+
+/*
+ * hs_plan -- group the terms into factors and fix every factor's diagonal
+ * set, on the host only (no device memory).  This is the structural dry run
+ * of Section 3.2: offsets are known before any storage exists.
+ *
+ * Grouping (the paper leaves it open; reading used here): Z-only terms
+ * (identity included) form the diagonal factor D = exp(-i dt E(x)).  The
+ * other terms are placed first-fit in input order: a term joins the first
+ * group all of whose members it commutes with and whose exact exponential
+ * prod_k (cos(c_k dt) I - i sin(c_k dt) P_k) still has at most `budget`
+ * numerically nonzero diagonals (entries with |value| <= 1e-15 count as
+ * zero); otherwise it opens a new group.  This applies the diagonal budget
+ * of Eq. 5 to each factor.  A step applies D first, then the groups in
+ * creation order (first-order product, Eq. 4).
+ *
+ *   n_qubits     1..30
+ *   n_terms      >= 1
+ *   pauli_terms  n_terms NUL-terminated strings of exactly n_qubits chars
+ *   coeffs       2*n_terms doubles, (re, im) per term; H must be Hermitian
+ *   t            total time; steps >= 1 Trotter steps; dt = t / steps
+ *   budget       >= 1, maximum diagonals per factor
+ *   flags        HS_MERGE_DIAG or 0
+ *   out          receives a handle that only supports the query calls
+ *                (describe/footprint/free); hs_evolve rejects it.
+ */
+hs_status hs_plan(int n_qubits, int n_terms, const char *const *pauli_terms,
+                  const double *coeffs, double t, int steps, int budget,
+                  unsigned flags, hs_factors *out);
+
+/*
+ * hs_build_factors -- hs_plan, then build every factor's coefficient
+ * diagonals on the device (Section 3.2 layout; paper's SpME diagonal case,
+ * Section 3.3, for D).  Entries are computed in FP64 on the GPU:
+ * U[r, r+d] = L[loc(r), loc(r+d)] (times D[r+d] for the factor carrying the
+ * diagonal terms) when r and r+d agree outside the factor's support, else 0;
+ * they are then stored as complex64 (dtype HS_C64, rounded to nearest) or
+ * complex128.  Each diagonal starts on a 256-byte boundary.  The library owns
+ * this memory until hs_free_factors.  The call synchronises `stream` before
+ * returning.
+ */
+hs_status hs_build_factors(int n_qubits, int n_terms, const char *const *pauli_terms,
+                           const double *coeffs, double t, int steps, int budget,
+                           hs_dtype dtype, unsigned flags, void *stream, hs_factors *out);
+
+/*
+ * hs_evolve -- psi <- (U_F ... U_1)^steps psi, in place, for `batch` states
+ * (device pointer to [batch][N] interleaved complex of the factors' dtype).
+ * Enqueues kernels on `stream` and returns; faults surface at the caller's
+ * next synchronisation.  May be called repeatedly: evolve(k) followed by
+ * evolve(steps - k) gives bit-identical results to evolve(steps).
+ * flags: HS_RENORM (FP64 norm after each step, applied as a scale when the
+ * next step loads the state, and once more at the end), HS_NO_FUSE.
+ * complex64 states accumulate in FP32 over ascending offsets; complex128 in
+ * FP64.  Results do not depend on the batch size or on fusion.
+ */
+hs_status hs_evolve(hs_factors f, void *psi, int batch, int steps, void *stream,
+                    unsigned flags);
+
+/* Description of a planned or built handle. */
+hs_status hs_factors_info(hs_factors f, int *n_qubits, int *n_factors, int *n_terms,
+                          int *n_diag_terms, int *dtype, double *dt, int *steps);
+/* Term indices of the diagonal factor D, in input order (cap entries max). */
+hs_status hs_diag_terms(hs_factors f, int *term_idx, int cap);
+/* Factor k (application order): whether it carries D, its group size, its
+ * number of diagonals, its support bit mask and its stored bytes. */
+hs_status hs_factor_info(hs_factors f, int k, int *has_diag, int *n_group_terms,
+                         int *n_diags, unsigned long long *support_mask, size_t *bytes);
+hs_status hs_factor_terms(hs_factors f, int k, int *term_idx, int cap);
+hs_status hs_factor_offsets(hs_factors f, int k, long long *offsets, int cap);
+/* Copy entries [start, start + count) of diagonal j (ascending-offset order)
+ * of factor k -- a diagonal holds N - |d| entries of the factors' dtype -- to
+ * host memory; synchronises `stream`. */
+hs_status hs_factor_copy_diagonal(hs_factors f, int k, int j, long long start, long long count,
+                                  void *host_dst, void *stream);
+/* Bytes of device memory an evolution of `batch` states needs: the stored
+ * diagonals, the caller's states and the library's workspace. */
+hs_status hs_footprint(hs_factors f, int batch, size_t *bytes);
+/* The launches one Trotter step makes for `batch` states with evolve `flags`:
+ * *n_launches receives their count; launch i applies factors
+ * [first_factor[i], first_factor[i] + n_factors[i]) (arrays of `cap`
+ * entries, may be NULL to query the count).  A launch of several factors is
+ * one fused kernel; batches above HS_MAX_BATCH repeat the list per chunk. */
+hs_status hs_step_launches(hs_factors f, int batch, unsigned flags, int *n_launches,
+                           int *first_factor, int *n_factors, int cap);
+/* Sets *violated to 1 if any in-place launch met a nonzero coefficient that
+ * couples rows of different tiles (never for factors built here); syncs. */
+hs_status hs_check(hs_factors f, void *stream, int *violated);
+hs_status hs_free_factors(hs_factors f);
+
+/*
+ * hs_dia_spmv -- y = A x for an arbitrary operator in the diagonal layout
+ * (Alg. 1), out of place, for `batch` vectors ([batch][N]).
+ *   n_diags     number of stored diagonals (1..64)
+ *   offsets     host array, strictly ascending, each in (-N, N)
+ *   diags       host array of n_diags device pointers; diags[j] holds
+ *               N - |offsets[j]| entries of `dtype`
+ *   x, y        device, [batch][N]; must not overlap
+ * Rows accumulate diagonals in ascending-offset order.
+ */
+hs_status hs_dia_spmv(int n_diags, const long long *offsets, const void *const *diags,
+                      const void *x, void *y, int batch, long long N, hs_dtype dtype,
+                      void *stream);
+
+/* FP64 squared norms of `batch` device states; out: host [batch]; syncs. */
+hs_status hs_norm2(const void *psi, int batch, long long N, hs_dtype dtype, void *stream,
+                   double *out);
+
+/*
+ * hs_fidelity -- state fidelity (Section 4.3, "State Fidelity"; the formula
+ * is not printed -- reading: F = |<phi|psi>|^2 / (<phi|phi><psi|psi>)),
+ * accumulated in FP64 in one pass over both device states.  phi and psi may
+ * have different dtypes.  out: host [batch][5] = Re<phi|psi>, Im<phi|psi>,
+ * <phi|phi>, <psi|psi>, F.  Syncs.
+ */
+hs_status hs_fidelity(const void *phi, int phi_dtype, const void *psi, int psi_dtype,
+                      int batch, long long N, void *stream, double *out);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *hs_last_error(void);
+int hs_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

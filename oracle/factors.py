@@ -17,6 +17,8 @@ Readings where the paper is silent (each is listed in the design notes):
   first existing group all of whose members it commutes with and whose
   exponential then still has <= budget diagonals; otherwise it opens a new
   group.  A single term whose own exponential exceeds the budget is an error.
+  A group may act on at most 10 qubits (its local unitary is a dense
+  2^k x 2^k matrix); a term that would push a group past that limit skips it.
 * ``num_diags`` counts numerically nonzero diagonals: offsets
   spr(b) - spr(a) over local-unitary entries |L[a, b]| > 1e-15, where spr
   spreads local bits onto the support's qubit positions.  Entries at or below
@@ -135,6 +137,8 @@ def first_fit(terms, budget: int, dt: float) -> Partition:
         placed = False
         for g in groups:
             if not all(commute(t, terms[j]) for j in g):
+                continue
+            if len(support_bits([terms[j] for j in g] + [t])) > MAX_SUPPORT:
                 continue
             if num_diags([terms[j] for j in g] + [t], dt) <= budget:
                 g.append(i)

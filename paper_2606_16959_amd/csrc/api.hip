@@ -1,0 +1,696 @@
+// C ABI of the hamsim library (declared in include/hamsim.h): handle
+// lifetime, device construction of the factor diagonals, the evolve loop
+// (launch planning: tile geometry and fusion of consecutive factors), the
+// generic DIA SpMV and the FP64 reductions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hs_internal.h"
+
+using hs::DiagDesc;
+using hs::Factor;
+using hs::Plan;
+using hs::TileArgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+hs_status fail(hs_status s, const std::string &m) {
+    g_err = m;
+    return s;
+}
+
+hs_status hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? HS_ENOMEM : HS_EDEVICE;
+}
+
+#define HS_HIP(call, what)                                  \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(e_, what);    \
+    } while (0)
+
+int ilog2(int64_t v) {
+    int l = 0;
+    while ((int64_t(1) << (l + 1)) <= v) ++l;
+    return l;
+}
+
+size_t elem_bytes(int dtype) { return dtype == HS_C128 ? 16 : 8; }
+
+// Tile geometry for coupling hull [lb, hb) of bits.
+struct Geo {
+    int qb = 0, kb = 0, logW = 0, nlw_log = 0, T = 0;
+    bool ok = false;
+};
+
+// Largest tile (rows) the kernel holds: 16 complex64 / 8 complex128
+// accumulators per thread, shared by the batch rounded up to a power of two.
+int tile_rows_max(int dtype, int batch) {
+    int bp = 1;
+    while (bp < batch) bp <<= 1;
+    const int te = dtype == HS_C128 ? 8 : 16;
+    return 256 * std::max(1, te / bp);
+}
+
+int w_min(int dtype) { return dtype == HS_C128 ? 16 : 32; }   // 256-byte row runs
+
+Geo geometry(int lb, int hb, int n, int Tmax) {
+    Geo g;
+    hb = std::min(hb, n);
+    lb = std::min(lb, hb);
+    const int logT = std::min(ilog2(Tmax), n);
+    if (hb <= logT) {               // contiguous tile of 2^logT rows
+        g.qb = 0; g.kb = logT; g.logW = 0; g.nlw_log = 0; g.T = 1 << logT; g.ok = true;
+        return g;
+    }
+    const int kb = hb - lb;
+    if (kb > logT) return g;
+    g.qb = lb;
+    g.kb = kb;
+    g.logW = std::min(logT - kb, lb);
+    g.nlw_log = lb - g.logW;
+    g.T = 1 << (kb + g.logW);
+    g.ok = true;
+    return g;
+}
+
+struct Run {
+    std::vector<int> factors;   // consecutive factor indices
+    Geo geo;
+    int launch_batch = 1;       // states per launch (1 when the chunk does not fit)
+    bool elementwise = false;   // a single main-diagonal factor
+    int desc_start = 0;
+    std::vector<int> dstart;    // per factor, relative to desc_start (size nf + 1)
+};
+
+struct EvolvePlan {
+    std::vector<Run> runs;
+    std::vector<DiagDesc> host_desc;
+    DiagDesc *dev_desc = nullptr;
+};
+
+}  // namespace
+
+struct hs_factors_s {
+    Plan plan;
+    bool built = false;
+    int dtype = HS_C64;
+    int device = 0;
+    int *viol_dev = nullptr;
+    double *work_dev = nullptr;      // [8][G][4] partials, then [8][4] records
+    std::map<std::pair<int, int>, EvolvePlan> plans;   // (chunk batch, fuse)
+    std::mutex mu;
+
+    double *partials() { return work_dev; }
+    double *records() { return work_dev + (size_t)HS_MAX_BATCH * hs::kReduceBlocks * 4; }
+
+    ~hs_factors_s() {
+        for (auto &f : plan.factors)
+            if (f.dev) (void)hipFree(f.dev);
+        for (auto &kv : plans)
+            if (kv.second.dev_desc) (void)hipFree(kv.second.dev_desc);
+        if (viol_dev) (void)hipFree(viol_dev);
+        if (work_dev) (void)hipFree(work_dev);
+    }
+};
+
+namespace {
+
+// Greedy fusion: extend a run while the union of coupling hulls still fits
+// one closed tile with rows runs of at least w_min elements.
+hs_status make_evolve_plan(hs_factors_s *h, int batch, bool fuse, EvolvePlan &ep, void *stream) {
+    const Plan &P = h->plan;
+    const int n = P.n;
+    const int Tmax = tile_rows_max(h->dtype, batch);
+    const int Wmin = w_min(h->dtype);
+    const size_t sc = elem_bytes(h->dtype);
+    ep = EvolvePlan();
+    const int F = (int)P.factors.size();
+    int f = 0;
+    while (f < F) {
+        Run run;
+        run.factors.push_back(f);
+        int lb = P.factors[f].xlb, hb = P.factors[f].xhb;
+        bool empty = P.factors[f].xmask_union == 0;
+        if (P.factors[f].offs.size() == 1 && P.factors[f].offs[0] == 0 && empty) {
+            run.elementwise = true;
+        }
+        int ndiag = (int)P.factors[f].offs.size();
+        int g = f + 1;
+        while (fuse && g < F && (int)run.factors.size() < hs::kMaxRun) {
+            const Factor &G = P.factors[g];
+            int nlb = lb, nhb = hb;
+            if (G.xmask_union) {
+                if (empty) { nlb = G.xlb; nhb = G.xhb; }
+                else { nlb = std::min(lb, G.xlb); nhb = std::max(hb, G.xhb); }
+            }
+            const Geo geo = geometry(nlb, nhb, n, Tmax);
+            const bool good = geo.ok && (geo.qb == 0 || (1 << geo.logW) >= Wmin);
+            if (!good || ndiag + (int)G.offs.size() > hs::kMaxDiagsPerLaunch) break;
+            run.factors.push_back(g);
+            run.elementwise = false;
+            ndiag += (int)G.offs.size();
+            lb = nlb; hb = nhb;
+            if (G.xmask_union) empty = false;
+            ++g;
+        }
+        run.launch_batch = batch;
+        run.geo = geometry(empty ? 0 : lb, empty ? 0 : hb, n, Tmax);
+        if (!run.geo.ok) {            // orbit wider than the batched tile: one state per launch
+            run.launch_batch = 1;
+            run.geo = geometry(lb, hb, n, tile_rows_max(h->dtype, 1));
+            if (!run.geo.ok) return fail(HS_ETOOLARGE, "factor coupling range does not fit a tile");
+        }
+        run.desc_start = (int)ep.host_desc.size();
+        run.dstart.push_back(0);
+        for (int k : run.factors) {
+            const Factor &Fk = P.factors[k];
+            for (size_t j = 0; j < Fk.offs.size(); ++j) {
+                const int64_t d = Fk.offs[j];
+                DiagDesc dd{};
+                dd.ptr = static_cast<const char *>(Fk.dev) + Fk.elem_off[j] * sc;
+                dd.off = (int32_t)d;
+                const int64_t lowmask = (int64_t(1) << run.geo.qb) - 1;
+                dd.regular = (d & lowmask) == 0;
+                dd.m = dd.regular ? (int32_t)(d >> run.geo.qb) : 0;
+                dd.lo = (int32_t)std::max<int64_t>(0, -d);
+                dd.hi = (int32_t)std::min<int64_t>(P.N, P.N - d);
+                ep.host_desc.push_back(dd);
+            }
+            run.dstart.push_back((int)(ep.host_desc.size() - run.desc_start));
+        }
+        ep.runs.push_back(run);
+        f = g;
+    }
+    const size_t bytes = ep.host_desc.size() * sizeof(DiagDesc);
+    HS_HIP(hipMalloc(&ep.dev_desc, std::max<size_t>(bytes, 64)), "hipMalloc(descriptors)");
+    // the host table lives as long as the plan, so an ordered async copy is safe
+    hipError_t e = hipMemcpyAsync(ep.dev_desc, ep.host_desc.data(), bytes, hipMemcpyHostToDevice,
+                                  reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        (void)hipFree(ep.dev_desc);
+        ep.dev_desc = nullptr;
+        return hip_fail(e, "hipMemcpy(descriptors)");
+    }
+    return HS_OK;
+}
+
+hs_status launch_run(hs_factors_s *h, const EvolvePlan &ep, const Run &run, void *psi, int chunk,
+                     const double *nrm2_records, void *stream) {
+    const Plan &P = h->plan;
+    const bool c128 = h->dtype == HS_C128;
+    const size_t sc = elem_bytes(h->dtype);
+    if (run.elementwise) {
+        const Factor &Fk = P.factors[run.factors[0]];
+        int e = hs::launch_diag_elementwise(psi, psi, Fk.dev, P.N, chunk, nrm2_records, c128, stream);
+        if (e) return hip_fail((hipError_t)e, "diag kernel launch");
+        return HS_OK;
+    }
+    const int lbatch = run.launch_batch;
+    for (int b0 = 0; b0 < chunk; b0 += lbatch) {
+        TileArgs a{};
+        char *p = static_cast<char *>(psi) + (size_t)b0 * P.N * sc;
+        a.y = p;
+        a.x = p;
+        a.stride = P.N;
+        a.N = (int32_t)P.N;
+        a.nf = (int32_t)run.factors.size();
+        for (int k = 0; k <= a.nf; ++k) a.dstart[k] = run.dstart[k];
+        a.desc = ep.dev_desc + run.desc_start;
+        a.qb = run.geo.qb;
+        a.kb = run.geo.kb;
+        a.logW = run.geo.logW;
+        a.nlw_log = run.geo.nlw_log;
+        a.T = run.geo.T;
+        a.nrm2 = nrm2_records ? nrm2_records + 4 * b0 : nullptr;
+        a.viol = h->viol_dev;
+        int e = hs::launch_tile(a, std::min(lbatch, chunk - b0), c128, true, stream);
+        if (e) return hip_fail((hipError_t)e, "tile kernel launch");
+    }
+    return HS_OK;
+}
+
+hs_status check_handle(hs_factors f) {
+    if (!f) return fail(HS_EINVAL, "null handle");
+    return HS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hs_last_error(void) { return g_err.c_str(); }
+int hs_abi_version(void) { return 1; }
+
+hs_status hs_plan(int n_qubits, int n_terms, const char *const *pauli_terms, const double *coeffs,
+                  double t, int steps, int budget, unsigned flags, hs_factors *out) {
+    if (!out) return fail(HS_EINVAL, "null output handle");
+    *out = nullptr;
+    hs_factors_s *h = new (std::nothrow) hs_factors_s();
+    if (!h) return fail(HS_ENOMEM, "host allocation failed");
+    std::string msg;
+    hs_status s = hs::make_plan(n_qubits, n_terms, pauli_terms, coeffs, t, steps, budget, flags,
+                                h->plan, msg);
+    if (s != HS_OK) {
+        delete h;
+        return fail(s, msg);
+    }
+    for (auto &f : h->plan.factors) hs::layout_factor(f, h->plan.N, 8);
+    *out = h;
+    g_err.clear();
+    return HS_OK;
+}
+
+static hs_status build_device(hs_factors_s *h, void *stream) {
+    Plan &P = h->plan;
+    const size_t sc = elem_bytes(h->dtype);
+    const bool c128 = h->dtype == HS_C128;
+    HS_HIP(hipGetDevice(&h->device), "hipGetDevice");
+    for (auto &f : P.factors) {
+        hs::layout_factor(f, P.N, sc);
+        HS_HIP(hipMalloc(&f.dev, f.elems_total * sc), "hipMalloc(factor diagonals)");
+    }
+    HS_HIP(hipMalloc(&h->viol_dev, sizeof(int)), "hipMalloc(flag)");
+    HS_HIP(hipMemset(h->viol_dev, 0, sizeof(int)), "hipMemset(flag)");
+    HS_HIP(hipMalloc(&h->work_dev, sizeof(double) * ((size_t)HS_MAX_BATCH * hs::kReduceBlocks * 4 + HS_MAX_BATCH * 4)),
+           "hipMalloc(workspace)");
+
+    // temporaries: phase table and per-factor tables
+    std::vector<void *> temps;
+    auto cleanup = [&]() {
+        for (void *p : temps) (void)hipFree(p);
+    };
+    auto upload = [&](const void *src, size_t bytes, void **dst) -> hipError_t {
+        hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 16));
+        if (e != hipSuccess) return e;
+        temps.push_back(*dst);
+        return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    double *phase = nullptr;
+    hipError_t e = hipSuccess;
+    if (!P.diag.empty()) {
+        std::vector<uint64_t> zm;
+        std::vector<double> cf;
+        for (int k : P.diag) {
+            zm.push_back(P.terms[k].z);
+            cf.push_back(P.terms[k].c);
+        }
+        void *dzm = nullptr, *dcf = nullptr;
+        if ((e = upload(zm.data(), zm.size() * 8, &dzm)) != hipSuccess ||
+            (e = upload(cf.data(), cf.size() * 8, &dcf)) != hipSuccess ||
+            (e = hipMalloc(reinterpret_cast<void **>(&phase), (size_t)P.N * 16)) != hipSuccess) {
+            cleanup();
+            return hip_fail(e, "phase table setup");
+        }
+        temps.push_back(phase);
+        int le = hs::launch_phase_table(P.N, (int)zm.size(), static_cast<uint64_t *>(dzm),
+                                        static_cast<double *>(dcf), P.dt, phase, stream);
+        if (le) { cleanup(); return hip_fail((hipError_t)le, "phase table kernel"); }
+    }
+    for (auto &f : P.factors) {
+        hs::ConstructArgs a{};
+        a.base = f.dev;
+        a.N = (int32_t)P.N;
+        a.smask = (uint32_t)f.smask;
+        std::vector<uint64_t> eo(f.elem_off.begin(), f.elem_off.end());
+        void *doffs = nullptr, *deo = nullptr, *dL = nullptr;
+        if ((e = upload(f.offs.data(), f.offs.size() * 8, &doffs)) != hipSuccess ||
+            (e = upload(eo.data(), eo.size() * 8, &deo)) != hipSuccess) {
+            cleanup();
+            return hip_fail(e, "factor table upload");
+        }
+        a.offs = static_cast<int64_t *>(doffs);
+        a.elem_off = static_cast<uint64_t *>(deo);
+        if (!f.terms.empty()) {
+            if ((e = upload(f.L.data(), f.L.size() * 16, &dL)) != hipSuccess) {
+                cleanup();
+                return hip_fail(e, "local unitary upload");
+            }
+            a.L = static_cast<double *>(dL);
+            a.K = 1 << f.bits.size();
+            a.nbits = (int)f.bits.size();
+            for (int q = 0; q < a.nbits; ++q) a.bits[q] = (int8_t)f.bits[q];
+            a.lb = f.bits.empty() ? 0 : f.bits[0];
+            a.contiguous = f.bits.empty() || f.bits.back() - f.bits.front() + 1 == (int)f.bits.size();
+        } else {
+            a.L = nullptr;
+            a.K = 1;
+        }
+        a.phase = f.has_diag ? phase : nullptr;
+        int le = hs::launch_construct(a, (int)f.offs.size(), P.N, c128, stream);
+        if (le) { cleanup(); return hip_fail((hipError_t)le, "construct kernel"); }
+    }
+    e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+    cleanup();
+    if (e != hipSuccess) return hip_fail(e, "construction");
+    h->built = true;
+    return HS_OK;
+}
+
+hs_status hs_build_factors(int n_qubits, int n_terms, const char *const *pauli_terms,
+                           const double *coeffs, double t, int steps, int budget, hs_dtype dtype,
+                           unsigned flags, void *stream, hs_factors *out) {
+    if (!out) return fail(HS_EINVAL, "null output handle");
+    *out = nullptr;
+    if (dtype != HS_C64 && dtype != HS_C128) return fail(HS_EINVAL, "dtype must be HS_C64 or HS_C128");
+    hs_factors h = nullptr;
+    hs_status s = hs_plan(n_qubits, n_terms, pauli_terms, coeffs, t, steps, budget, flags, &h);
+    if (s != HS_OK) return s;
+    h->dtype = dtype;
+    s = build_device(h, stream);
+    if (s != HS_OK) {
+        std::string keep = g_err;
+        delete h;
+        g_err = keep;
+        return s;
+    }
+    *out = h;
+    g_err.clear();
+    return HS_OK;
+}
+
+hs_status hs_evolve(hs_factors f, void *psi, int batch, int steps, void *stream, unsigned flags) {
+    if (hs_status s = check_handle(f)) return s;
+    if (!f->built) return fail(HS_EINVAL, "handle was planned, not built");
+    if (!psi) return fail(HS_EINVAL, "null state pointer");
+    if (batch < 1) return fail(HS_EINVAL, "batch must be >= 1");
+    if (steps < 0) return fail(HS_EINVAL, "steps must be >= 0");
+    if (flags & ~(unsigned)(HS_RENORM | HS_NO_FUSE)) return fail(HS_EINVAL, "unknown evolve flag");
+    if (steps == 0) return HS_OK;
+    std::lock_guard<std::mutex> lock(f->mu);
+    const Plan &P = f->plan;
+    const size_t sc = elem_bytes(f->dtype);
+    const bool fuse = !(flags & HS_NO_FUSE);
+    const bool renorm = (flags & HS_RENORM) != 0;
+    int cur_dev = 0;
+    HS_HIP(hipGetDevice(&cur_dev), "hipGetDevice");
+    if (cur_dev != f->device) return fail(HS_EINVAL, "current device differs from the build device");
+    for (int c0 = 0; c0 < batch; c0 += HS_MAX_BATCH) {
+        const int chunk = std::min(HS_MAX_BATCH, batch - c0);
+        auto key = std::make_pair(chunk, fuse ? 1 : 0);
+        auto it = f->plans.find(key);
+        if (it == f->plans.end()) {
+            EvolvePlan ep;
+            if (hs_status s = make_evolve_plan(f, chunk, fuse, ep, stream)) return s;
+            it = f->plans.emplace(key, std::move(ep)).first;
+        }
+        const EvolvePlan &ep = it->second;
+        void *p = static_cast<char *>(psi) + (size_t)c0 * P.N * sc;
+        const double *rec = f->records() + 2;    // squared norm of state b at rec[4 b]
+        for (int s = 0; s < steps; ++s) {
+            for (size_t ri = 0; ri < ep.runs.size(); ++ri) {
+                const double *nrm = (renorm && s > 0 && ri == 0) ? rec : nullptr;
+                if (hs_status st = launch_run(f, ep, ep.runs[ri], p, chunk, nrm, stream)) return st;
+            }
+            if (renorm) {
+                int e = hs::launch_reduce(p, f->dtype, p, f->dtype, chunk, P.N, f->partials(),
+                                          hs::kReduceBlocks, f->records(), false, stream);
+                if (e) return hip_fail((hipError_t)e, "norm reduction");
+            }
+        }
+        if (renorm) {
+            int e = hs::launch_scale(p, P.N, chunk, rec, f->dtype == HS_C128, stream);
+            if (e) return hip_fail((hipError_t)e, "scale kernel");
+        }
+    }
+    return HS_OK;
+}
+
+hs_status hs_factors_info(hs_factors f, int *n_qubits, int *n_factors, int *n_terms,
+                          int *n_diag_terms, int *dtype, double *dt, int *steps) {
+    if (hs_status s = check_handle(f)) return s;
+    if (n_qubits) *n_qubits = f->plan.n;
+    if (n_factors) *n_factors = (int)f->plan.factors.size();
+    if (n_terms) *n_terms = (int)f->plan.terms.size();
+    if (n_diag_terms) *n_diag_terms = (int)f->plan.diag.size();
+    if (dtype) *dtype = f->dtype;
+    if (dt) *dt = f->plan.dt;
+    if (steps) *steps = f->plan.steps;
+    return HS_OK;
+}
+
+hs_status hs_diag_terms(hs_factors f, int *term_idx, int cap) {
+    if (hs_status s = check_handle(f)) return s;
+    if (cap < (int)f->plan.diag.size() || (!term_idx && !f->plan.diag.empty()))
+        return fail(HS_EINVAL, "output too small");
+    std::copy(f->plan.diag.begin(), f->plan.diag.end(), term_idx);
+    return HS_OK;
+}
+
+static hs_status get_factor(hs_factors f, int k, const Factor **out) {
+    if (hs_status s = check_handle(f)) return s;
+    if (k < 0 || k >= (int)f->plan.factors.size()) return fail(HS_EINVAL, "factor index out of range");
+    *out = &f->plan.factors[k];
+    return HS_OK;
+}
+
+hs_status hs_factor_info(hs_factors f, int k, int *has_diag, int *n_group_terms, int *n_diags,
+                         unsigned long long *support_mask, size_t *bytes) {
+    const Factor *F = nullptr;
+    if (hs_status s = get_factor(f, k, &F)) return s;
+    if (has_diag) *has_diag = F->has_diag ? 1 : 0;
+    if (n_group_terms) *n_group_terms = (int)F->terms.size();
+    if (n_diags) *n_diags = (int)F->offs.size();
+    if (support_mask) *support_mask = F->smask;
+    if (bytes) *bytes = F->elems_total * elem_bytes(f->dtype);
+    return HS_OK;
+}
+
+hs_status hs_factor_terms(hs_factors f, int k, int *term_idx, int cap) {
+    const Factor *F = nullptr;
+    if (hs_status s = get_factor(f, k, &F)) return s;
+    if (cap < (int)F->terms.size() || (!term_idx && !F->terms.empty())) return fail(HS_EINVAL, "output too small");
+    std::copy(F->terms.begin(), F->terms.end(), term_idx);
+    return HS_OK;
+}
+
+hs_status hs_factor_offsets(hs_factors f, int k, long long *offsets, int cap) {
+    const Factor *F = nullptr;
+    if (hs_status s = get_factor(f, k, &F)) return s;
+    if (cap < (int)F->offs.size() || !offsets) return fail(HS_EINVAL, "output too small");
+    for (size_t j = 0; j < F->offs.size(); ++j) offsets[j] = (long long)F->offs[j];
+    return HS_OK;
+}
+
+hs_status hs_factor_copy_diagonal(hs_factors f, int k, int j, long long start, long long count,
+                                  void *host_dst, void *stream) {
+    const Factor *F = nullptr;
+    if (hs_status s = get_factor(f, k, &F)) return s;
+    if (!f->built) return fail(HS_EINVAL, "handle was planned, not built");
+    if (j < 0 || j >= (int)F->offs.size()) return fail(HS_EINVAL, "diagonal index out of range");
+    const int64_t d = F->offs[j];
+    const long long len = f->plan.N - (d < 0 ? -d : d);
+    if (start < 0 || count < 0 || start + count > len || !host_dst)
+        return fail(HS_EINVAL, "range outside the diagonal's N - |d| entries");
+    if (count == 0) return HS_OK;
+    const size_t sc = elem_bytes(f->dtype);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    HS_HIP(hipMemcpyAsync(host_dst, static_cast<char *>(F->dev) + (F->elem_off[j] + (size_t)start) * sc,
+                          (size_t)count * sc, hipMemcpyDeviceToHost, st), "hipMemcpyAsync(diagonal)");
+    HS_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return HS_OK;
+}
+
+hs_status hs_step_launches(hs_factors f, int batch, unsigned flags, int *n_launches,
+                           int *first_factor, int *n_factors, int cap) {
+    if (hs_status s = check_handle(f)) return s;
+    if (!f->built) return fail(HS_EINVAL, "handle was planned, not built");
+    if (batch < 1 || !n_launches) return fail(HS_EINVAL, "batch >= 1 and an output are required");
+    if (flags & ~(unsigned)(HS_RENORM | HS_NO_FUSE)) return fail(HS_EINVAL, "unknown evolve flag");
+    std::lock_guard<std::mutex> lock(f->mu);
+    const int chunk = std::min(HS_MAX_BATCH, batch);
+    const bool fuse = !(flags & HS_NO_FUSE);
+    auto key = std::make_pair(chunk, fuse ? 1 : 0);
+    auto it = f->plans.find(key);
+    if (it == f->plans.end()) {
+        EvolvePlan ep;
+        if (hs_status s = make_evolve_plan(f, chunk, fuse, ep, nullptr)) return s;
+        it = f->plans.emplace(key, std::move(ep)).first;
+        HS_HIP(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
+    }
+    const auto &runs = it->second.runs;
+    *n_launches = (int)runs.size();
+    if (first_factor && n_factors) {
+        if (cap < (int)runs.size()) return fail(HS_EINVAL, "output too small");
+        for (size_t i = 0; i < runs.size(); ++i) {
+            first_factor[i] = runs[i].factors.front();
+            n_factors[i] = (int)runs[i].factors.size();
+        }
+    }
+    return HS_OK;
+}
+
+hs_status hs_footprint(hs_factors f, int batch, size_t *bytes) {
+    if (hs_status s = check_handle(f)) return s;
+    if (batch < 1 || !bytes) return fail(HS_EINVAL, "batch >= 1 and an output are required");
+    const size_t sc = elem_bytes(f->dtype);
+    size_t total = 0;
+    for (const auto &F : f->plan.factors) {
+        const size_t align = hs::kDiagAlignBytes / sc;
+        for (int64_t d : F.offs) {
+            const size_t len = (size_t)(f->plan.N - (d < 0 ? -d : d));
+            total += (len + align - 1) / align * align * sc;
+        }
+    }
+    total += (size_t)batch * f->plan.N * sc;                         // the states
+    total += sizeof(double) * ((size_t)HS_MAX_BATCH * hs::kReduceBlocks * 4 + HS_MAX_BATCH * 4);
+    total += 64 * 1024;                                               // descriptors, flag
+    *bytes = total;
+    return HS_OK;
+}
+
+hs_status hs_check(hs_factors f, void *stream, int *violated) {
+    if (hs_status s = check_handle(f)) return s;
+    if (!f->built || !violated) return fail(HS_EINVAL, "built handle and output required");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int v = 0;
+    HS_HIP(hipMemcpyAsync(&v, f->viol_dev, sizeof(int), hipMemcpyDeviceToHost, st), "hipMemcpyAsync(flag)");
+    HS_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    *violated = v;
+    return HS_OK;
+}
+
+hs_status hs_free_factors(hs_factors f) {
+    if (!f) return HS_OK;
+    delete f;
+    return HS_OK;
+}
+
+hs_status hs_dia_spmv(int n_diags, const long long *offsets, const void *const *diags, const void *x,
+                      void *y, int batch, long long N, hs_dtype dtype, void *stream) {
+    if (dtype != HS_C64 && dtype != HS_C128) return fail(HS_EINVAL, "bad dtype");
+    if (n_diags < 1 || n_diags > 64 || !offsets || !diags || !x || !y || batch < 1)
+        return fail(HS_EINVAL, "bad arguments");
+    if (N < 1 || N > (1ll << HS_MAX_QUBITS) || (N & (N - 1)))
+        return fail(HS_EINVAL, "N must be a power of two <= 2^30");
+    const size_t sc = elem_bytes(dtype);
+    const char *xb = static_cast<const char *>(x);
+    char *yb = static_cast<char *>(y);
+    const size_t span = (size_t)batch * N * sc;
+    if (xb < yb + span && yb < xb + span) return fail(HS_EINVAL, "x and y overlap");
+    uint64_t orall = 0;
+    long long maxabs = 0;
+    for (int j = 0; j < n_diags; ++j) {
+        if (offsets[j] <= -N || offsets[j] >= N) return fail(HS_EINVAL, "offset out of range");
+        if (j && offsets[j] <= offsets[j - 1]) return fail(HS_EINVAL, "offsets must ascend strictly");
+        if (!diags[j]) return fail(HS_EINVAL, "null diagonal pointer");
+        const long long a = offsets[j] < 0 ? -offsets[j] : offsets[j];
+        orall |= (uint64_t)a;
+        maxabs = std::max(maxabs, a);
+    }
+    const int n = ilog2(N);
+    const int chunk_max = HS_MAX_BATCH;
+    std::vector<DiagDesc> hd(n_diags);
+    for (int c0 = 0; c0 < batch; c0 += chunk_max) {
+        const int chunk = std::min(chunk_max, batch - c0);
+        const int Tmax = tile_rows_max(dtype, chunk);
+        // Stride the tile by the largest power of two dividing every offset
+        // when that keeps 256-byte row runs; otherwise use contiguous tiles.
+        int q = orall ? __builtin_ctzll(orall) : 0;
+        Geo geo = geometry(0, 0, n, Tmax);
+        if (orall && (1 << std::min(q, 20)) >= w_min(dtype) && maxabs >= Tmax) {
+            const int need = ilog2(maxabs >> q) + 1;     // levels reaching the farthest offset
+            const int logT = std::min(ilog2(Tmax), n);
+            const int kb = std::min(need + 1, logT - ilog2(w_min(dtype)));
+            if (kb >= 1) {
+                Geo g2 = geometry(q, q + kb, n, Tmax);
+                if (g2.ok && g2.qb > 0) geo = g2;
+            }
+        }
+        for (int j = 0; j < n_diags; ++j) {
+            const long long d = offsets[j];
+            DiagDesc &dd = hd[j];
+            dd = DiagDesc{};
+            dd.ptr = diags[j];
+            dd.off = (int32_t)d;
+            const long long lowmask = (1ll << geo.qb) - 1;
+            dd.regular = (d & lowmask) == 0;
+            dd.m = dd.regular ? (int32_t)(d >> geo.qb) : 0;
+            dd.lo = (int32_t)std::max<long long>(0, -d);
+            dd.hi = (int32_t)std::min<long long>(N, N - d);
+        }
+        DiagDesc *ddev = nullptr;
+        HS_HIP(hipMalloc(&ddev, sizeof(DiagDesc) * n_diags), "hipMalloc(descriptors)");
+        hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+        hipError_t e = hipMemcpyAsync(ddev, hd.data(), sizeof(DiagDesc) * n_diags, hipMemcpyHostToDevice, st);
+        TileArgs a{};
+        a.y = yb + (size_t)c0 * N * sc;
+        a.x = xb + (size_t)c0 * N * sc;
+        a.stride = N;
+        a.N = (int32_t)N;
+        a.nf = 1;
+        a.dstart[0] = 0;
+        a.dstart[1] = n_diags;
+        a.desc = ddev;
+        a.qb = geo.qb; a.kb = geo.kb; a.logW = geo.logW; a.nlw_log = geo.nlw_log; a.T = geo.T;
+        a.nrm2 = nullptr;
+        a.viol = nullptr;
+        if (e == hipSuccess) {
+            int le = hs::launch_tile(a, chunk, dtype == HS_C128, false, stream);
+            e = (hipError_t)le;
+        }
+        hipError_t e2 = hipStreamSynchronize(st);
+        (void)hipFree(ddev);
+        if (e != hipSuccess) return hip_fail(e, "dia_spmv launch");
+        if (e2 != hipSuccess) return hip_fail(e2, "dia_spmv");
+    }
+    return HS_OK;
+}
+
+static hs_status reduce_call(const void *A, int ta, const void *B, int tb, int batch, long long N,
+                             void *stream, bool dot, std::vector<double> &rec) {
+    const int G = hs::kReduceBlocks;
+    double *work = nullptr;
+    HS_HIP(hipMalloc(&work, sizeof(double) * ((size_t)batch * G * 4 + (size_t)batch * 4)), "hipMalloc(reduce)");
+    double *out = work + (size_t)batch * G * 4;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int le = hs::launch_reduce(A, ta, B, tb, batch, N, work, G, out, dot, stream);
+    rec.assign((size_t)batch * 4, 0.0);
+    hipError_t e = (hipError_t)le;
+    if (e == hipSuccess) e = hipMemcpyAsync(rec.data(), out, sizeof(double) * batch * 4, hipMemcpyDeviceToHost, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    (void)hipFree(work);
+    if (e != hipSuccess) return hip_fail(e, "reduction");
+    if (e2 != hipSuccess) return hip_fail(e2, "reduction");
+    return HS_OK;
+}
+
+hs_status hs_norm2(const void *psi, int batch, long long N, hs_dtype dtype, void *stream, double *out) {
+    if (!psi || !out || batch < 1 || N < 1) return fail(HS_EINVAL, "bad arguments");
+    if (dtype != HS_C64 && dtype != HS_C128) return fail(HS_EINVAL, "bad dtype");
+    std::vector<double> rec;
+    if (hs_status s = reduce_call(psi, dtype, psi, dtype, batch, N, stream, false, rec)) return s;
+    for (int b = 0; b < batch; ++b) out[b] = rec[4 * b + 2];
+    return HS_OK;
+}
+
+hs_status hs_fidelity(const void *phi, int phi_dtype, const void *psi, int psi_dtype, int batch,
+                      long long N, void *stream, double *out) {
+    if (!phi || !psi || !out || batch < 1 || N < 1) return fail(HS_EINVAL, "bad arguments");
+    for (int t : {phi_dtype, psi_dtype})
+        if (t != HS_C64 && t != HS_C128) return fail(HS_EINVAL, "bad dtype");
+    std::vector<double> rec;
+    if (hs_status s = reduce_call(phi, phi_dtype, psi, psi_dtype, batch, N, stream, true, rec)) return s;
+    for (int b = 0; b < batch; ++b) {
+        const double re = rec[4 * b], im = rec[4 * b + 1], np = rec[4 * b + 2], nq = rec[4 * b + 3];
+        out[5 * b + 0] = re;
+        out[5 * b + 1] = im;
+        out[5 * b + 2] = np;
+        out[5 * b + 3] = nq;
+        out[5 * b + 4] = (re * re + im * im) / (np * nq);
+    }
+    return HS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Internal structures of the hamsim library (host planning + device launch).
+#pragma once
+
+#include <complex>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hamsim.h"
+
+namespace hs {
+
+constexpr double kTau = 1e-15;          // |L[a,b]| <= kTau counts as zero
+constexpr int kMaxRun = 8;              // factors fused into one launch
+constexpr int kMaxDiagsPerLaunch = 128; // descriptors per launch
+constexpr size_t kDiagAlignBytes = 256; // start of every stored diagonal
+
+struct Term {
+    uint64_t x = 0, z = 0;  // X-part and Z-part masks (Y sets both)
+    int ny = 0;             // number of Y characters
+    double c = 0.0;         // real coefficient
+};
+
+struct Factor {
+    bool has_diag = false;          // carries D = exp(-i dt E(x)) on the right
+    std::vector<int> terms;         // member term indices (application order)
+    std::vector<int64_t> offs;      // ascending diagonal offsets d = col - row
+    uint64_t smask = 0;             // support (X or Z bits of any member)
+    std::vector<int> bits;          // support bits, ascending
+    uint64_t xmask_union = 0;       // bits any member flips
+    int xlb = 0, xhb = 0;           // hull [xlb, xhb) of xmask_union (empty: 0,0)
+    std::vector<std::complex<double>> L;  // K x K local unitary, row-major
+    std::vector<size_t> elem_off;   // element offset of each diagonal
+    size_t elems_total = 0;         // elements incl. alignment padding
+    void *dev = nullptr;            // device buffer (built handles)
+};
+
+struct Plan {
+    int n = 0;
+    int64_t N = 0;
+    double t = 0.0, dt = 0.0;
+    int steps = 0, budget = 0;
+    unsigned flags = 0;
+    std::vector<Term> terms;
+    std::vector<int> diag;          // Z-only term indices
+    std::vector<Factor> factors;    // application order
+};
+
+// Host-side planning (no device calls).  Returns HS_OK or an error with msg.
+hs_status make_plan(int n_qubits, int n_terms, const char *const *strings, const double *coeffs,
+                    double t, int steps, int budget, unsigned flags, Plan &out, std::string &msg);
+void layout_factor(Factor &f, int64_t N, size_t elem_bytes);
+
+// ------------------------------------------------------------------ kernels
+
+// One stored diagonal as seen by the tile kernel.
+struct DiagDesc {
+    const void *ptr;   // entries, element type = state element type
+    int32_t off;       // d
+    int32_t m;         // d >> qb when regular
+    int32_t regular;   // d is a multiple of 2^qb
+    int32_t lo, hi;    // rows r with 0 <= r + d < N: [lo, hi)
+    int32_t pad;
+};
+
+struct TileArgs {
+    void *y;
+    const void *x;
+    int64_t stride;          // elements between consecutive states (= N)
+    int32_t N;
+    int32_t nf;              // factors in this launch
+    int32_t dstart[kMaxRun + 1];
+    const DiagDesc *desc;
+    int32_t qb, kb, logW, nlw_log, T;
+    const double *nrm2;      // per-state squared norms to divide out, or null
+    int *viol;               // closure-violation flag (closed launches)
+};
+
+struct ConstructArgs {
+    void *base;              // factor buffer
+    const int64_t *offs;     // [nd]
+    const uint64_t *elem_off;// [nd]
+    const double *L;         // K*K interleaved complex
+    const double *phase;     // N interleaved complex, or null
+    int32_t N;
+    int32_t K;
+    uint32_t smask;
+    int32_t contiguous;      // support is [lb, lb+k)
+    int32_t lb;
+    int32_t nbits;
+    int8_t bits[16];
+};
+
+// launchers (kernels.hip); all return hipError_t as int
+int launch_phase_table(int64_t N, int nz, const uint64_t *zm, const double *cf, double dt,
+                       double *out, void *stream);
+int launch_construct(const ConstructArgs &a, int nd, int64_t max_len, bool c128, void *stream);
+int launch_tile(const TileArgs &a, int batch, bool c128, bool closed, void *stream);
+int launch_diag_elementwise(void *y, const void *x, const void *diag, int64_t N, int batch,
+                            const double *nrm2, bool c128, void *stream);
+int launch_reduce(const void *A, int ta, const void *B, int tb, int batch, int64_t N,
+                  double *partial, int G, double *out, bool dot, void *stream);
+int launch_scale(void *psi, int64_t N, int batch, const double *nrm2, bool c128, void *stream);
+
+constexpr int kReduceBlocks = 1024;   // partial sums per state (fixed: determinism)
+
+}  // namespace hs

@@ -1,0 +1,435 @@
+// HIP kernels for gfx950 (MI355X): factor construction, the DIA tile kernel
+// (single factor or a fused run of factors), the single-diagonal kernel and
+// the FP64 reductions.  The state update is bandwidth-bound (about one
+// complex FMA per stored coefficient), so nothing here uses MFMA; the
+// kernels are built around coalesced 8/16-byte streams along each diagonal,
+// LDS staging of the state tile and wave64 shuffle reductions.
+#include <hip/hip_runtime.h>
+
+#include "hs_internal.h"
+
+namespace hs {
+
+template <typename R>
+struct alignas(2 * sizeof(R)) C2 {
+    R re, im;
+};
+
+// acc += c * x, in a fixed order of fused multiply-adds (the same in every
+// kernel, so results do not depend on which kernel or batch size ran).
+__device__ __forceinline__ void cfma(C2<float> &acc, C2<float> c, C2<float> x) {
+    acc.re = __builtin_fmaf(c.re, x.re, acc.re);
+    acc.re = __builtin_fmaf(-c.im, x.im, acc.re);
+    acc.im = __builtin_fmaf(c.re, x.im, acc.im);
+    acc.im = __builtin_fmaf(c.im, x.re, acc.im);
+}
+__device__ __forceinline__ void cfma(C2<double> &acc, C2<double> c, C2<double> x) {
+    acc.re = __builtin_fma(c.re, x.re, acc.re);
+    acc.re = __builtin_fma(-c.im, x.im, acc.re);
+    acc.im = __builtin_fma(c.re, x.im, acc.im);
+    acc.im = __builtin_fma(c.im, x.re, acc.im);
+}
+
+template <typename R>
+__device__ __forceinline__ C2<R> cscale(C2<R> v, R s) {
+    return C2<R>{v.re * s, v.im * s};
+}
+
+// nrm2 points at the squared norm of state 0 inside [batch][4] reduction
+// records (state b at nrm2[4 b]); null means no rescaling.
+template <typename R>
+__device__ __forceinline__ R inv_norm(const double *nrm2, int b) {
+    return nrm2 ? (R)(1.0 / sqrt(nrm2[4 * b])) : (R)1;
+}
+
+// ------------------------------------------------------------ construction
+
+// E(x) = sum_k c_k (-1)^{popcount(x & z_k)};  out[x] = exp(-i dt E(x)), FP64.
+__global__ void phase_table_kernel(int64_t N, int nz, const uint64_t *__restrict__ zm,
+                                   const double *__restrict__ cf, double dt,
+                                   double *__restrict__ out) {
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < N;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        double E = 0.0;
+        for (int k = 0; k < nz; ++k) E += cf[k] * ((__popcll((uint64_t)x & zm[k]) & 1) ? -1.0 : 1.0);
+        double s, c;
+        sincos(-dt * E, &s, &c);
+        out[2 * x] = c;
+        out[2 * x + 1] = s;
+    }
+}
+
+// One diagonal per blockIdx.y.  Entry i of diagonal d sits at row r = i - min(d, 0),
+// column p = r + d.  Value: L[loc(r), loc(p)] (times D[p]) when r and p agree
+// outside the support, else exactly 0; computed in FP64, stored as R.
+template <typename R>
+__global__ void construct_kernel(ConstructArgs a) {
+    const int j = blockIdx.y;
+    const int64_t d = a.offs[j];
+    const int64_t len = (int64_t)a.N - (d < 0 ? -d : d);
+    const int64_t neg = d < 0 ? d : 0;
+    C2<R> *out = reinterpret_cast<C2<R> *>(a.base) + a.elem_off[j];
+    const uint64_t outside = ~(uint64_t)a.smask;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i - neg, p = r + d;
+        double vr = 0.0, vi = 0.0;
+        if (a.L == nullptr) {
+            if (r == p) vr = 1.0;
+        } else if ((((uint64_t)(r ^ p)) & outside) == 0) {
+            uint32_t la = 0, lb = 0;
+            if (a.contiguous) {
+                la = (uint32_t)(r >> a.lb) & (uint32_t)(a.K - 1);
+                lb = (uint32_t)(p >> a.lb) & (uint32_t)(a.K - 1);
+            } else {
+                for (int q = 0; q < a.nbits; ++q) {
+                    la |= (uint32_t)((r >> a.bits[q]) & 1) << q;
+                    lb |= (uint32_t)((p >> a.bits[q]) & 1) << q;
+                }
+            }
+            const int64_t e = (int64_t)la * a.K + lb;
+            vr = a.L[2 * e];
+            vi = a.L[2 * e + 1];
+        }
+        if (a.phase && (vr != 0.0 || vi != 0.0)) {
+            const double pr = a.phase[2 * p], pi = a.phase[2 * p + 1];
+            const double tr = vr * pr - vi * pi;
+            const double ti = vr * pi + vi * pr;
+            vr = tr;
+            vi = ti;
+        }
+        out[i] = C2<R>{(R)vr, (R)vi};
+    }
+}
+
+// ------------------------------------------------------------ DIA tile kernel
+//
+// A workgroup owns one tile of T = 2^kb * W rows:
+//   row(i) = hi * 2^(qb+kb) + (i >> logW) * 2^qb + lw * W + (i & (W-1)),
+// i.e. all 2^kb "levels" of the bits [qb, qb+kb) times a window of W
+// consecutive low rows (contiguous tiles: qb = 0, W = 1, T = 2^kb).
+// The state rows of the tile (all B states) are staged once into LDS with
+// coalesced loads.  Every row then sums, in ascending-offset order, the stored
+// coefficient of each diagonal times the partner amplitude x[r + d]: from LDS
+// when the partner row lies in the tile, else (open launches) from global
+// memory if the coefficient is nonzero.  Every stored coefficient is read
+// exactly once, by the thread that owns its row, along the diagonal in
+// consecutive addresses.
+//
+// Closed launches (factors built by this library, whose nonzeros only couple
+// rows inside one tile) run in place and do not read outside the tile: a
+// nonzero out-of-tile coefficient only raises the violation flag.  A fused
+// launch applies several factors in turn on the tile held in LDS.
+template <typename R, int B, int RPT, bool CLOSED>
+__global__ __launch_bounds__(256) void dia_tile_kernel(TileArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<R> *lds = reinterpret_cast<C2<R> *>(smem_raw);
+    const int T = a.T;
+    const int tid = threadIdx.x;
+    const int qb = a.qb, kb = a.kb, logW = a.logW;
+    const int W = 1 << logW;
+    const int L = 1 << kb;
+    const int blk = blockIdx.x;
+    const int hi = blk >> a.nlw_log;
+    const int lw = blk & ((1 << a.nlw_log) - 1);
+    const int base = (hi << (qb + kb)) | (lw << logW);
+    const C2<R> *x = reinterpret_cast<const C2<R> *>(a.x);  // may alias y (in place)
+    C2<R> *y = reinterpret_cast<C2<R> *>(a.y);
+
+    R scale[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) scale[b] = inv_norm<R>(a.nrm2, b);
+
+    // stage the tile
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = tid + j * 256;
+        if (i < T) {
+            const int r = base + ((i >> logW) << qb) + (i & (W - 1));
+#pragma unroll
+            for (int b = 0; b < B; ++b) lds[b * T + i] = cscale(x[b * a.stride + r], scale[b]);
+        }
+    }
+    __syncthreads();
+
+    C2<R> acc[RPT][B];
+    bool viol = false;
+    for (int f = 0; f < a.nf; ++f) {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j)
+#pragma unroll
+            for (int b = 0; b < B; ++b) acc[j][b] = C2<R>{(R)0, (R)0};
+
+        for (int dj = a.dstart[f]; dj < a.dstart[f + 1]; ++dj) {
+            const DiagDesc dd = a.desc[dj];
+            const C2<R> *__restrict__ cp = reinterpret_cast<const C2<R> *>(dd.ptr);
+            const int neg = dd.off < 0 ? dd.off : 0;
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const int i = tid + j * 256;
+                if (i >= T) continue;
+                const int r = base + ((i >> logW) << qb) + (i & (W - 1));
+                if (r < dd.lo || r >= dd.hi) continue;       // no entry on this diagonal
+                bool in;
+                int loc;
+                const int p = r + dd.off;
+                if (dd.regular) {
+                    const int lvl = (i >> logW) + dd.m;
+                    in = (unsigned)lvl < (unsigned)L;
+                    loc = i + dd.m * W;
+                } else {
+                    in = (p >> (qb + kb)) == hi && ((p & ((1 << qb) - 1)) >> logW) == lw;
+                    loc = (((p >> qb) & (L - 1)) << logW) | (p & (W - 1));
+                }
+                const C2<R> c = cp[r + neg];
+                if (in) {
+#pragma unroll
+                    for (int b = 0; b < B; ++b) cfma(acc[j][b], c, lds[b * T + loc]);
+                } else if (c.re != (R)0 || c.im != (R)0) {
+                    if (CLOSED) {
+                        viol = true;
+                    } else {
+#pragma unroll
+                        for (int b = 0; b < B; ++b) cfma(acc[j][b], c, cscale(x[b * a.stride + p], scale[b]));
+                    }
+                }
+            }
+        }
+        if (f + 1 < a.nf) {
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const int i = tid + j * 256;
+                if (i < T)
+#pragma unroll
+                    for (int b = 0; b < B; ++b) lds[b * T + i] = acc[j][b];
+            }
+            __syncthreads();
+        }
+    }
+
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = tid + j * 256;
+        if (i < T) {
+            const int r = base + ((i >> logW) << qb) + (i & (W - 1));
+#pragma unroll
+            for (int b = 0; b < B; ++b) y[b * a.stride + r] = acc[j][b];
+        }
+    }
+    if (CLOSED && viol) atomicOr(a.viol, 1);
+}
+
+// Single main-diagonal factor: y[i] = v[i] x[i] (in place allowed).
+template <typename R, int B>
+__global__ __launch_bounds__(256) void diag_elementwise_kernel(C2<R> *y, const C2<R> *x,
+                                                               const C2<R> *__restrict__ v,
+                                                               int64_t N, const double *nrm2) {
+    R scale[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) scale[b] = inv_norm<R>(nrm2, b);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const C2<R> c = v[i];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            C2<R> acc{(R)0, (R)0};
+            cfma(acc, c, cscale(x[b * N + i], scale[b]));
+            y[b * N + i] = acc;
+        }
+    }
+}
+
+template <typename R>
+__global__ void scale_kernel(C2<R> *psi, int64_t N, const double *nrm2) {
+    const int b = blockIdx.y;
+    const R s = inv_norm<R>(nrm2, b);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x)
+        psi[b * N + i] = cscale(psi[b * N + i], s);
+}
+
+// ------------------------------------------------------------ reductions
+// Pass 1: block g of state b sums elements g*256+t, stepping by G*256, in
+// FP64; wave64 butterfly, then the four waves in fixed order.  Pass 2: one
+// block per state sums the G partials in a fixed tree.  No atomics, so the
+// result is bit-reproducible.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename TA, typename TB, bool DOT>
+__global__ __launch_bounds__(256) void reduce_partial_kernel(const void *A, const void *Bv, int64_t N,
+                                                             int G, double *partial) {
+    const int b = blockIdx.y;
+    const C2<TA> *pa = reinterpret_cast<const C2<TA> *>(A) + b * N;
+    const C2<TB> *pb = reinterpret_cast<const C2<TB> *>(Bv) + b * N;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)G * 256) {
+        const C2<TA> u = pa[i];
+        const double ar = (double)u.re, ai = (double)u.im;
+        s[2] += ar * ar + ai * ai;
+        if (DOT) {
+            const C2<TB> w = pb[i];
+            const double br = (double)w.re, bi = (double)w.im;
+            s[0] += ar * br + ai * bi;
+            s[1] += ar * bi - ai * br;
+            s[3] += br * br + bi * bi;
+        }
+    }
+    __shared__ double red[4][4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double v = wave_sum(s[k]);
+        if (lane == 0) red[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        partial[((int64_t)b * G + blockIdx.x) * 4 + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    }
+}
+
+__global__ __launch_bounds__(256) void reduce_final_kernel(const double *partial, int G, double *out) {
+    const int b = blockIdx.x;
+    __shared__ double red[256][4];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int g = threadIdx.x; g < G; g += 256)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] += partial[((int64_t)b * G + g) * 4 + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[threadIdx.x][k] = s[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[threadIdx.x][k] += red[threadIdx.x + w][k];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[b * 4 + threadIdx.x] = red[0][threadIdx.x];
+}
+
+// ------------------------------------------------------------ launchers
+
+static inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+static inline int grid_for(int64_t n, int per_block, int cap) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+int launch_phase_table(int64_t N, int nz, const uint64_t *zm, const double *cf, double dt,
+                       double *out, void *stream) {
+    hipLaunchKernelGGL(phase_table_kernel, dim3(grid_for(N, 256, 1 << 20)), dim3(256), 0, S(stream),
+                       N, nz, zm, cf, dt, out);
+    return (int)hipGetLastError();
+}
+
+int launch_construct(const ConstructArgs &a, int nd, int64_t max_len, bool c128, void *stream) {
+    dim3 grid(grid_for(max_len, 256, 1 << 16), nd);
+    if (c128)
+        hipLaunchKernelGGL(construct_kernel<double>, grid, dim3(256), 0, S(stream), a);
+    else
+        hipLaunchKernelGGL(construct_kernel<float>, grid, dim3(256), 0, S(stream), a);
+    return (int)hipGetLastError();
+}
+
+template <typename R, int B, int RPT>
+static void tile_dispatch_closed(const TileArgs &a, bool closed, void *stream) {
+    const size_t lds = (size_t)a.T * B * sizeof(C2<R>);
+    const int grid = (int)(a.N / a.T);
+    if (closed)
+        hipLaunchKernelGGL((dia_tile_kernel<R, B, RPT, true>), dim3(grid), dim3(256), lds, S(stream), a);
+    else
+        hipLaunchKernelGGL((dia_tile_kernel<R, B, RPT, false>), dim3(grid), dim3(256), lds, S(stream), a);
+}
+
+// rows per thread: 16 (complex64) or 8 (complex128) accumulators per thread,
+// split over the batch rounded up to a power of two.
+template <typename R>
+static int tile_dispatch(const TileArgs &a, int batch, bool closed, void *stream) {
+    constexpr int TE = sizeof(R) == 4 ? 16 : 8;
+    switch (batch) {
+        case 1: tile_dispatch_closed<R, 1, TE>(a, closed, stream); break;
+        case 2: tile_dispatch_closed<R, 2, TE / 2>(a, closed, stream); break;
+        case 3: tile_dispatch_closed<R, 3, TE / 4>(a, closed, stream); break;
+        case 4: tile_dispatch_closed<R, 4, TE / 4>(a, closed, stream); break;
+        case 5: tile_dispatch_closed<R, 5, (TE / 8 > 0 ? TE / 8 : 1)>(a, closed, stream); break;
+        case 6: tile_dispatch_closed<R, 6, (TE / 8 > 0 ? TE / 8 : 1)>(a, closed, stream); break;
+        case 7: tile_dispatch_closed<R, 7, (TE / 8 > 0 ? TE / 8 : 1)>(a, closed, stream); break;
+        case 8: tile_dispatch_closed<R, 8, (TE / 8 > 0 ? TE / 8 : 1)>(a, closed, stream); break;
+        default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_tile(const TileArgs &a, int batch, bool c128, bool closed, void *stream) {
+    return c128 ? tile_dispatch<double>(a, batch, closed, stream)
+                : tile_dispatch<float>(a, batch, closed, stream);
+}
+
+template <typename R>
+static int diag_dispatch(void *y, const void *x, const void *v, int64_t N, int batch,
+                         const double *nrm2, void *stream) {
+    C2<R> *py = reinterpret_cast<C2<R> *>(y);
+    const C2<R> *px = reinterpret_cast<const C2<R> *>(x);
+    const C2<R> *pv = reinterpret_cast<const C2<R> *>(v);
+    const dim3 g(grid_for(N, 256, 1 << 16)), blk(256);
+    switch (batch) {
+#define HS_DIAG_CASE(BB) \
+    case BB: hipLaunchKernelGGL((diag_elementwise_kernel<R, BB>), g, blk, 0, S(stream), py, px, pv, N, nrm2); break;
+        HS_DIAG_CASE(1) HS_DIAG_CASE(2) HS_DIAG_CASE(3) HS_DIAG_CASE(4)
+        HS_DIAG_CASE(5) HS_DIAG_CASE(6) HS_DIAG_CASE(7) HS_DIAG_CASE(8)
+#undef HS_DIAG_CASE
+        default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_diag_elementwise(void *y, const void *x, const void *diag, int64_t N, int batch,
+                            const double *nrm2, bool c128, void *stream) {
+    return c128 ? diag_dispatch<double>(y, x, diag, N, batch, nrm2, stream)
+                : diag_dispatch<float>(y, x, diag, N, batch, nrm2, stream);
+}
+
+int launch_scale(void *psi, int64_t N, int batch, const double *nrm2, bool c128, void *stream) {
+    dim3 g(grid_for(N, 256, 1 << 14), batch);
+    if (c128)
+        hipLaunchKernelGGL(scale_kernel<double>, g, dim3(256), 0, S(stream),
+                           reinterpret_cast<C2<double> *>(psi), N, nrm2);
+    else
+        hipLaunchKernelGGL(scale_kernel<float>, g, dim3(256), 0, S(stream),
+                           reinterpret_cast<C2<float> *>(psi), N, nrm2);
+    return (int)hipGetLastError();
+}
+
+int launch_reduce(const void *A, int ta, const void *Bv, int tb, int batch, int64_t N,
+                  double *partial, int G, double *out, bool dot, void *stream) {
+    dim3 g(G, batch), blk(256);
+    if (!dot) {
+        if (ta == HS_C128)
+            hipLaunchKernelGGL((reduce_partial_kernel<double, double, false>), g, blk, 0, S(stream), A, A, N, G, partial);
+        else
+            hipLaunchKernelGGL((reduce_partial_kernel<float, float, false>), g, blk, 0, S(stream), A, A, N, G, partial);
+    } else {
+        if (ta == HS_C128 && tb == HS_C128)
+            hipLaunchKernelGGL((reduce_partial_kernel<double, double, true>), g, blk, 0, S(stream), A, Bv, N, G, partial);
+        else if (ta == HS_C128)
+            hipLaunchKernelGGL((reduce_partial_kernel<double, float, true>), g, blk, 0, S(stream), A, Bv, N, G, partial);
+        else if (tb == HS_C128)
+            hipLaunchKernelGGL((reduce_partial_kernel<float, double, true>), g, blk, 0, S(stream), A, Bv, N, G, partial);
+        else
+            hipLaunchKernelGGL((reduce_partial_kernel<float, float, true>), g, blk, 0, S(stream), A, Bv, N, G, partial);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(batch), blk, 0, S(stream), partial, G, out);
+    return (int)hipGetLastError();
+}
+
+}  // namespace hs

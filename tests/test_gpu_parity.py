@@ -1,0 +1,334 @@
+"""GPU parity: the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances.  complex128 runs are compared element by element within
+1e-12 (well above accumulated FP64 rounding for these sizes) and by fidelity
+>= 1 - 1e-12.  complex64 runs store coefficients rounded to FP32 and
+accumulate in FP32: per element the error is bounded by a small multiple of
+2^-24 * sum_d |c_d| |x_{r+d}| per launch, checked as 2^-20 * that sum; whole
+evolutions are checked by fidelity >= 1 - 1e-6 against the oracle.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import fid, hs_gpu, note, oracle_run, oracle_threads, tol_c64
+from oracle import dia as odia, factors as ofac, metrics, pauli as opauli
+from workloads import config_hamiltonian, hamiltonians as wh, states as ws
+
+pytestmark = pytest.mark.gpu
+
+
+def _to_dev(torch, a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a.astype(dtype))).cuda()
+
+
+def _heis10():
+    return wh.heisenberg_1d(10, 1.0, fields=np.linspace(-0.9, 0.7, 10))
+
+
+# ------------------------------------------------------------------ (a0) construction
+
+@pytest.mark.parametrize("case,dtype,merge", [
+    ("cfg1", "c128", True), ("cfg1", "c64", True), ("heis10", "c128", False), ("heis10", "c64", True),
+])
+def test_construction_matches_oracle_entries(case, dtype, merge):
+    hs, torch = hs_gpu()
+    if case == "cfg1":
+        H, budget, t, steps = config_hamiltonian(1), 8, 1.0, 10
+    else:
+        H, budget, t, steps = _heis10(), 16, 0.7, 9
+    note(f"construct {case} {dtype} merge={merge}")
+    f = hs.build_factors(H.strings, H.coeffs, H.n, t, steps, budget, dtype=dtype, merge_diag=merge)
+    terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
+    part = ofac.first_fit(terms, budget, t / steps)
+    desc = f.describe()
+    N = 1 << H.n
+    for k, (fd, fo) in enumerate(zip(desc["factors"], part.factor_list(merge_diag=merge))):
+        for j, d in enumerate(fd["offsets"]):
+            got = f.copy_diagonal(k, j, d).astype(np.complex128)
+            rows = np.arange(N - abs(d)) - min(d, 0)        # storage index i -> row i - min(d, 0)
+            ref = ofac.factor_entries(terms, part, fo, H.n, t / steps, rows, d)
+            # structural zeros are exact zeros
+            assert np.array_equal(got == 0, ref == 0), (k, d)
+            if dtype == "c128":
+                assert np.abs(got - ref).max() <= 1e-15
+            else:
+                assert np.all(np.abs(got - ref) <= 2.0 ** -24 * np.abs(ref) * 1.5 + 1e-30)
+    f.close()
+
+
+def test_construction_sampled_at_full_size_config3():
+    hs, torch = hs_gpu()
+    H = config_hamiltonian(3)
+    note("construct config3 n=26 c64 (sampled windows)")
+    f = hs.build_factors(H.strings, H.coeffs, H.n, 1.0, 50, 16, dtype="c64")
+    terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
+    part = ofac.first_fit(terms, 16, 1.0 / 50)
+    desc = f.describe()
+    N = 1 << 26
+    rng = np.random.default_rng(3)
+    for k, (fd, fo) in enumerate(zip(desc["factors"], part.factor_list())):
+        for j, d in enumerate(fd["offsets"]):
+            length = N - abs(d)
+            for start in [0, length - 512] + list(rng.integers(0, length - 512, 2)):
+                got = f.copy_diagonal(k, j, d, start=int(start), count=512).astype(np.complex128)
+                rows = np.arange(start, start + 512) - min(d, 0)
+                ref = ofac.factor_entries(terms, part, fo, 26, 0.02, rows, d)
+                assert np.array_equal(got == 0, ref == 0)
+                assert np.all(np.abs(got - ref) <= 2.0 ** -24 * np.abs(ref) * 1.5 + 1e-30)
+    f.close()
+
+
+# ------------------------------------------------------------------ (a1) generic DIA SpMV
+
+def _random_dia(rng, N, offsets, dtype):
+    diags = []
+    for d in offsets:
+        v = rng.normal(size=N - abs(d)) + 1j * rng.normal(size=N - abs(d))
+        v[rng.random(N - abs(d)) < 0.1] = 0.0
+        diags.append(v.astype(dtype))
+    return diags
+
+
+@pytest.mark.parametrize("N,B,dtype,kind", [
+    (2, 1, "c128", "all"), (1 << 10, 1, "c128", "near"), (1 << 14, 3, "c64", "near"),
+    (1 << 16, 1, "c64", "far"), (1 << 16, 8, "c64", "far"), (1 << 15, 2, "c128", "strided"),
+    (1 << 16, 1, "c64", "strided"), (1 << 13, 5, "c128", "mixed"), (1 << 12, 11, "c64", "mixed"),
+])
+def test_dia_spmv_matches_definition(N, B, dtype, kind):
+    hs, torch = hs_gpu()
+    rng = np.random.default_rng(N + B)
+    npd = np.complex128 if dtype == "c128" else np.complex64
+    if kind == "all":
+        offs = list(range(-(N - 1), N))
+    elif kind == "near":
+        offs = sorted(set(rng.integers(-9, 10, 7).tolist()) | {0})
+    elif kind == "far":            # includes |d| >= N/2 and the extreme offsets
+        offs = sorted({-(N - 1), -(N // 2), -3, 0, 5, N // 2 + 7, N - 1})
+    elif kind == "strided":        # multiples of 64 reaching far: strided tiles
+        offs = sorted({-64 * 37, -128, 0, 64, 64 * 5, 64 * 200})
+    else:
+        offs = sorted(set(rng.integers(-N + 1, N, 12).tolist()))
+    diags = _random_dia(rng, N, offs, npd)
+    x = (rng.normal(size=(B, N)) + 1j * rng.normal(size=(B, N))).astype(npd)
+    note(f"dia_spmv N={N} B={B} {dtype} {kind}")
+    y = hs.dia_spmv(offs, [_to_dev(torch, v, npd) for v in diags], _to_dev(torch, x, npd))
+    got = y.cpu().numpy().astype(np.complex128)
+    D = {d: v.astype(np.complex128) for d, v in zip(offs, diags)}
+    ref = odia.dia_spmv(D, x.astype(np.complex128))
+    bound = odia.dia_spmv({d: np.abs(v) for d, v in D.items()}, np.abs(x.astype(np.complex128)))
+    fac = 1e-14 if dtype == "c128" else tol_c64()
+    assert np.all(np.abs(got - ref) <= fac * bound + 1e-300)
+
+
+def test_dia_spmv_rejects_overlap_and_bad_offsets():
+    hs, torch = hs_gpu()
+    x = torch.zeros(64, dtype=torch.complex64, device="cuda")
+    v = torch.zeros(64, dtype=torch.complex64, device="cuda")
+    with pytest.raises(hs.HamsimError):
+        hs.dia_spmv([0], [v], x, y=x)
+    with pytest.raises(hs.HamsimError):
+        hs.dia_spmv([1, 0], [v[:63], v], x)
+
+
+# ------------------------------------------------------------------ (a2) evolution
+
+def _evolve_vs_oracle(H, budget, t, steps, psi0, dtype, run_steps=None, **kw):
+    hs, torch = hs_gpu()
+    npd = np.complex128 if dtype == "c128" else np.complex64
+    psi0 = np.atleast_2d(psi0).astype(npd)
+    f = hs.build_factors(H.strings, H.coeffs, H.n, t, steps, budget, dtype=dtype)
+    psi = _to_dev(torch, psi0, npd)
+    hs.evolve(f, psi, steps if run_steps is None else run_steps, **kw)
+    got = psi.cpu().numpy().astype(np.complex128)
+    assert f.check_closure()
+    f.close()
+    ref = oracle_run(H, budget, t, steps, psi0.astype(np.complex128), run_steps, threads=oracle_threads())
+    return got, ref
+
+
+def test_evolve_config1_complex128():
+    note("evolve config1 c128")
+    H = config_hamiltonian(1)
+    got, ref = _evolve_vs_oracle(H, 8, 1.0, 10, ws.zero_state(8), "c128")
+    assert np.abs(got - ref).max() <= 1e-12
+    assert fid(got, ref)[0] >= 1 - 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_evolve_config2(dtype):
+    note(f"evolve config2 {dtype}")
+    H = config_hamiltonian(2)
+    got, ref = _evolve_vs_oracle(H, 16, 2.0, 100, ws.neel_state(20), dtype)
+    F = fid(got, ref)[0]
+    if dtype == "c128":
+        assert F >= 1 - 1e-12 and np.abs(got - ref).max() <= 1e-12
+    else:
+        assert F >= 1 - 1e-6
+
+
+def test_evolve_config3_full_size_few_steps():
+    note("evolve config3 n=26 c64, 2 of 50 steps, vs oracle")
+    H = config_hamiltonian(3)
+    psi0 = ws.random_phase_state(26, 3, np.complex64)
+    got, ref = _evolve_vs_oracle(H, 16, 1.0, 50, psi0, "c64", run_steps=2)
+    assert fid(got, ref)[0] >= 1 - 1e-6
+    bound = 2e-6 * np.abs(ref).max()
+    assert np.abs(got - ref).max() <= bound
+
+
+def test_evolve_config4_full_size_batched():
+    hs, torch = hs_gpu()
+    note("evolve config4 n=24 B=8 c64, 2 of 200 steps, vs oracle + column invariance")
+    H = config_hamiltonian(4)
+    psi0 = ws.config_states(4, np.complex64)
+    got, ref = _evolve_vs_oracle(H, 16, 1.0, 200, psi0, "c64", run_steps=2)
+    assert np.all(fid(got, ref) >= 1 - 1e-6)
+    # column b of the batched run equals the single-state run, bit for bit
+    f = hs.build_factors(H.strings, H.coeffs, 24, 1.0, 200, 16, dtype="c64")
+    for b in (0, 5):
+        one = _to_dev(torch, psi0[b:b + 1], np.complex64)
+        hs.evolve(f, one, 2)
+        assert np.array_equal(one.cpu().numpy()[0], got[b].astype(np.complex64))
+    f.close()
+
+
+def test_fused_unfused_split_and_repeat_are_bitwise_equal():
+    hs, torch = hs_gpu()
+    H = config_hamiltonian(2)
+    note("bitwise: fused/unfused/split/repeat config2 c64")
+    f = hs.build_factors(H.strings, H.coeffs, 20, 2.0, 100, 16, dtype="c64")
+    psi0 = _to_dev(torch, ws.neel_state(20, np.complex64)[None], np.complex64)
+    runs = []
+    for fuse in (True, False):
+        p = psi0.clone()
+        hs.evolve(f, p, 30, fuse=fuse)
+        runs.append(p.cpu().numpy())
+    p = psi0.clone()
+    hs.evolve(f, p, 11)
+    hs.evolve(f, p, 19)
+    runs.append(p.cpu().numpy())
+    p = psi0.clone()
+    hs.evolve(f, p, 30)
+    runs.append(p.cpu().numpy())
+    for r in runs[1:]:
+        assert np.array_equal(r, runs[0])
+    f.close()
+
+
+def test_renorm_keeps_unit_norm_and_fidelity():
+    hs, torch = hs_gpu()
+    H = config_hamiltonian(2)
+    note("renorm config2 c64")
+    f = hs.build_factors(H.strings, H.coeffs, 20, 2.0, 100, 16, dtype="c64")
+    psi0 = ws.neel_state(20, np.complex64)[None]
+    p = _to_dev(torch, psi0, np.complex64)
+    hs.evolve(f, p, 100, renorm=True)
+    n2 = hs.norm2(p)[0]
+    assert abs(n2 - 1.0) < 1e-6
+    q = _to_dev(torch, psi0, np.complex64)
+    hs.evolve(f, q, 40, renorm=True)
+    hs.evolve(f, q, 60, renorm=True)
+    assert np.array_equal(q.cpu().numpy(), p.cpu().numpy())
+    ref = oracle_run(H, 16, 2.0, 100, psi0.astype(np.complex128), threads=oracle_threads())
+    assert fid(p.cpu().numpy().astype(np.complex128), ref)[0] >= 1 - 1e-6
+    f.close()
+
+
+# ------------------------------------------------------------------ (a3) single diagonal
+
+def test_diagonal_only_hamiltonian_matches_closed_form():
+    hs, torch = hs_gpu()
+    rng = np.random.Generator(np.random.PCG64(5))
+    d = rng.uniform(1, 10, (4, 4))
+    d = np.triu(d, 1) + np.triu(d, 1).T
+    H = wh.tsp_onehot(d, 20.0)
+    note("diagonal-only TSP n=16 c64 and c128")
+    terms = opauli.parse_terms(H.strings, H.coeffs, 16)
+    E = ofac.energies(terms, list(range(len(terms))), 16)
+    psi0 = ws.random_phase_state(16, 11)
+    exact = np.exp(-1j * 1.0 * E) * psi0
+    for dtype, tol in (("c128", 1e-12), ("c64", 2e-5)):
+        npd = np.complex128 if dtype == "c128" else np.complex64
+        f = hs.build_factors(H.strings, H.coeffs, 16, 1.0, 20, 16, dtype=dtype)
+        assert f.n_factors == 1 and f.describe()["factors"][0]["offsets"] == [0]
+        p = _to_dev(torch, psi0[None], npd)
+        hs.evolve(f, p, 20)
+        got = p.cpu().numpy()[0].astype(np.complex128)
+        assert np.abs(got - exact).max() <= tol * np.abs(exact).max()
+        f.close()
+
+
+# ------------------------------------------------------------------ (a5, a6) reductions
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_norm_and_fidelity_reductions(dtype):
+    hs, torch = hs_gpu()
+    npd = np.complex128 if dtype == "c128" else np.complex64
+    rng = np.random.default_rng(9)
+    for N, B in ((1, 1), (1000, 3), (1 << 20, 2)):
+        note(f"reductions N={N} B={B} {dtype}")
+        a = (rng.normal(size=(B, N)) + 1j * rng.normal(size=(B, N))).astype(npd)
+        b = (rng.normal(size=(B, N)) + 1j * rng.normal(size=(B, N))).astype(npd)
+        da, db = _to_dev(torch, a, npd), _to_dev(torch, b, npd)
+        n2 = hs.norm2(da)
+        ref = metrics.norm2(a.astype(np.complex128))
+        assert np.all(np.abs(n2 - ref) <= 1e-13 * ref)
+        assert np.array_equal(n2, hs.norm2(da))            # deterministic
+        out = hs.fidelity(da, db)
+        ov = metrics.inner(a.astype(np.complex128), b.astype(np.complex128))
+        assert np.all(np.abs(out[:, 0] - ov.real) <= 1e-12 * np.sqrt(ref * metrics.norm2(b)))
+        assert np.all(np.abs(out[:, 1] - ov.imag) <= 1e-12 * np.sqrt(ref * metrics.norm2(b)))
+        fref = metrics.fidelity(a.astype(np.complex128), b.astype(np.complex128))
+        assert np.all(np.abs(out[:, 4] - fref) <= 1e-12)
+    # mixed precision: complex64 against complex128
+    a = (rng.normal(size=(1, 4096)) + 1j * rng.normal(size=(1, 4096)))
+    out = hs.fidelity(_to_dev(torch, a, np.complex64), _to_dev(torch, a, np.complex128))
+    assert out[0, 4] == pytest.approx(metrics.fidelity(a.astype(np.complex64).astype(np.complex128), a)[0], abs=1e-14)
+
+
+# ------------------------------------------------------------------ degenerate cases
+
+def test_degenerate_cases():
+    hs, torch = hs_gpu()
+    note("degenerate: identity-only, n=1, steps=0, odd batches")
+    # identity-only Hamiltonian: a global phase e^{-i c t}
+    f = hs.build_factors(["III"], [0.7], 3, 2.0, 5, 1, dtype="c128")
+    p = _to_dev(torch, ws.uniform_state(3)[None], np.complex128)
+    hs.evolve(f, p, 5)
+    assert np.allclose(p.cpu().numpy()[0], np.exp(-1.4j) * ws.uniform_state(3), atol=1e-14)
+    hs.evolve(f, p, 0)
+    f.close()
+    # one qubit, X field: exact rotation
+    f = hs.build_factors(["X"], [0.3], 1, 1.0, 4, 3, dtype="c128")
+    p = _to_dev(torch, ws.zero_state(1)[None], np.complex128)
+    hs.evolve(f, p, 4)
+    assert np.allclose(p.cpu().numpy()[0], [np.cos(0.3), -1j * np.sin(0.3)], atol=1e-15)
+    f.close()
+    # batch sizes that are not powers of two, and above the launch limit of 8
+    H = _heis10()
+    f = hs.build_factors(H.strings, H.coeffs, 10, 0.5, 5, 16, dtype="c64")
+    states = np.stack([ws.random_phase_state(10, s, np.complex64) for s in range(11)])
+    p = _to_dev(torch, states, np.complex64)
+    hs.evolve(f, p, 5)
+    got = p.cpu().numpy()
+    for b in (0, 2, 10):
+        q = _to_dev(torch, states[b:b + 1], np.complex64)
+        hs.evolve(f, q, 5)
+        assert np.array_equal(q.cpu().numpy()[0], got[b])
+    ref = oracle_run(H, 16, 0.5, 5, states.astype(np.complex128))
+    assert np.all(fid(got.astype(np.complex128), ref) >= 1 - 1e-6)
+    f.close()
+
+
+def test_merge_flag_does_not_change_the_result():
+    hs, torch = hs_gpu()
+    note("merge on/off config1 c128")
+    H = config_hamiltonian(1)
+    outs = []
+    for merge in (True, False):
+        f = hs.build_factors(H.strings, H.coeffs, 8, 1.0, 10, 8, dtype="c128", merge_diag=merge)
+        p = _to_dev(torch, ws.zero_state(8)[None], np.complex128)
+        hs.evolve(f, p, 10)
+        outs.append(p.cpu().numpy()[0])
+        f.close()
+    assert np.abs(outs[0] - outs[1]).max() <= 1e-13

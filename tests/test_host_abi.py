@@ -1,0 +1,141 @@
+"""The C-ABI library on the CPU: it loads, exports every declared symbol, and
+its host-side planning (grouping, diagonal sets, storage) matches the oracle
+exactly.  No device calls are made here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import factors as ofac, pauli as opauli
+from workloads import config_hamiltonian, hamiltonians as wh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def hs():
+    import paper_2606_16959_amd as hs
+    from paper_2606_16959_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2606_16959_amd import build
+        build.build()
+    return hs
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "hamsim.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(hs):
+    from paper_2606_16959_amd import _lib
+    names = _declared_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding declares a signature for each of them
+    assert set(names) <= set(_lib._SIG)
+    assert lib.hs_abi_version() == 1
+
+
+def _oracle_partition(H, budget, t, steps):
+    terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
+    return terms, ofac.first_fit(terms, budget, t / steps)
+
+
+def _check_plan_matches_oracle(hs, H, budget, t, steps, merge=True):
+    f = hs.plan(H.strings, H.coeffs, H.n, t, steps, budget, merge_diag=merge)
+    desc = f.describe()
+    terms, part = _oracle_partition(H, budget, t, steps)
+    assert desc["diag_terms"] == part.diag
+    fl = part.factor_list(merge_diag=merge)
+    assert len(desc["factors"]) == len(fl)
+    for got, (has_diag, g) in zip(desc["factors"], fl):
+        assert got["has_diag"] == has_diag
+        assert got["terms"] == g
+        assert got["offsets"] == ofac.factor_offsets(terms, (has_diag, g), t / steps)
+        # bytes: every diagonal N-|d| complex64 entries, each start 256-byte aligned
+        exp = sum(-(-(H.n and (1 << H.n) - abs(d)) // 32) * 32 * 8 for d in got["offsets"])
+        assert got["bytes"] == exp
+    f.close()
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
+def test_plan_matches_oracle_on_configs(hs, cfg):
+    H = config_hamiltonian(cfg)
+    run = wh.CONFIG_RUN[cfg]
+    _check_plan_matches_oracle(hs, H, run["budget"], run["t"], run["steps"])
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_plan_matches_oracle_on_random_hamiltonians(hs, seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(3, 9))
+    nt = int(rng.integers(1, 18))
+    alphabet = list("IXYZ") if seed % 2 else list("IIXZ")
+    strings = ["".join(rng.choice(alphabet, size=n)) for _ in range(nt)]
+    # identical coefficients on some terms so that cancellations occur
+    coeffs = np.round(rng.uniform(-1, 1, nt), 1)
+    H = wh.Hamiltonian(n, list(zip(strings, coeffs)))
+    budget = int(rng.choice([4, 8, 16, 64]))
+    t, steps = float(rng.uniform(0.1, 2)), int(rng.integers(1, 50))
+    try:
+        _oracle_partition(H, budget, t, steps)
+    except ofac.BudgetError:
+        with pytest.raises(hs.HamsimError) as ei:
+            hs.plan(H.strings, H.coeffs, n, t, steps, budget)
+        assert ei.value.status == 3
+        return
+    _check_plan_matches_oracle(hs, H, budget, t, steps, merge=bool(seed % 3))
+
+
+def test_plan_heisenberg_and_tsp_families(hs):
+    _check_plan_matches_oracle(hs, wh.heisenberg_1d(9, 1.0, fields=np.linspace(-1, 1, 9), periodic=True),
+                               16, 1.0, 10)
+    d = np.array([[0, 3, 4, 5], [3, 0, 6, 7], [4, 6, 0, 8], [5, 7, 8, 0]], float)
+    _check_plan_matches_oracle(hs, wh.tsp_onehot(d, 20.0), 16, 1.0, 20)
+
+
+def test_error_statuses(hs):
+    bad = [
+        (dict(strings=["XX"], coeffs=[1.0], n=3), 1),               # wrong length
+        (dict(strings=["XQ"], coeffs=[1.0], n=2), 1),               # bad character
+        (dict(strings=["XX"], coeffs=[1.0 + 0.5j], n=2), 2),        # non-Hermitian
+        (dict(strings=["XXX"], coeffs=[1.0], n=3, budget=8), 3),   # 9 diagonals > 8
+        (dict(strings=["X" * 31], coeffs=[1.0], n=31), 6),         # too many qubits
+        (dict(strings=["X" * 11 + "I"], coeffs=[1.0], n=12, budget=1 << 12), 6),  # support > 10
+        (dict(strings=["XX"], coeffs=[1.0], n=2, steps=0), 1),
+        (dict(strings=["XX"], coeffs=[1.0], n=2, budget=0), 1),
+        (dict(strings=["XX"], coeffs=[float("nan")], n=2), 1),
+    ]
+    for kw, status in bad:
+        args = dict(t=1.0, steps=10, budget=16)
+        args.update(kw)
+        with pytest.raises(hs.HamsimError) as ei:
+            hs.plan(args["strings"], args["coeffs"], args["n"], args["t"], args["steps"], args["budget"])
+        assert ei.value.status == status, (kw, str(ei.value))
+        assert str(ei.value)
+
+
+def test_planned_handle_cannot_evolve(hs):
+    from paper_2606_16959_amd import _lib
+    f = hs.plan(["XX", "ZZ"], [1.0, 0.5], 2, 1.0, 4, 16)
+    st = _lib.load().hs_evolve(f.handle, ctypes.c_void_p(1), 1, 1, None, 0)
+    assert st == 1 and b"planned" in _lib.load().hs_last_error()
+    assert _lib.load().hs_evolve(None, ctypes.c_void_p(1), 1, 1, None, 0) == 1
+
+
+def test_footprint_counts_diagonals_states_and_workspace(hs):
+    H = config_hamiltonian(3)
+    f = hs.plan(H.strings, H.coeffs, H.n, 1.0, 50, 16)
+    desc = f.describe()
+    diag_bytes = sum(x["bytes"] for x in desc["factors"])
+    N = 1 << 26
+    # 120.5 N complex64 entries of coefficients, within alignment padding
+    assert abs(diag_bytes - 120.5 * N * 8) < 64 * 256
+    fp1, fp8 = f.footprint(1), f.footprint(8)
+    assert fp1 >= diag_bytes + N * 8 and fp8 - fp1 == 7 * N * 8
