@@ -59,16 +59,18 @@ def launch_bytes(desc, launches, N, batch, elem):
     return out
 
 
-def measured_traffic(per_launch_bytes):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+def measured_traffic(per_launch_bytes, n_launches):
+    """Average HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+    from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source and launch plan; else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         t = json.load(fh)
-    if t.get("kernel_sha") != kernel_hash():
+    per = t.get("bytes_per_launch_scaled") or []
+    if t.get("kernel_sha") != kernel_hash() or len(per) != n_launches:
         return None
-    return t.get("bytes_per_launch_scaled")
+    return int(sum(per) / len(per))
 
 
 def copy_bandwidth(torch, nbytes=1 << 31, reps=10):
@@ -113,6 +115,106 @@ def cpu_baseline(H, psi0_c64, budget, t, steps_total, sample_steps, step_bytes):
     }
 
 
+def serve_leg(torch, n_jobs, rate, slots, oracle_nmax):
+    """Served stream (seeded Poisson arrivals of mixed-family jobs) and the
+    oracle check of a 5% sample (jobs whose id hashes into the sample and
+    whose n <= oracle_nmax; state column 0)."""
+    from oracle import evolve as oev, factors as ofac, metrics, pauli as opauli
+    from paper_2606_16959_amd.serve import Job, Server
+    from workloads.serve_stream import job_stream
+    specs = job_stream(n_jobs=n_jobs, rate=rate, seed=5)
+    sample = {s.job_id for s in specs
+              if int(hashlib.sha256(f"5:{s.job_id}".encode()).hexdigest(), 16) % 20 == 0}
+    jobs = []
+    for sp in specs:
+        H = sp.hamiltonian()
+        jobs.append(Job(sp.job_id, H.strings, H.coeffs, H.n, sp.t, sp.steps, sp.batch, sp.state_seed,
+                        arrival=sp.arrival, keep_result=sp.job_id in sample and sp.n <= oracle_nmax,
+                        tag=sp.family))
+    log(f"serve: {n_jobs} jobs at {rate}/s on {slots} slots")
+    res, st = Server(slots=slots).run(jobs)
+    log(f"serve: p50 {st['latency_ms']['p50']:.1f} ms p99 {st['latency_ms']['p99']:.1f} ms "
+        f"{st['throughput_jobs_s']:.1f} jobs/s")
+    worst, checked = 1.0, 0
+    for sp, job, r in zip(specs, jobs, res):
+        if not job.keep_result or r.status != "ok":
+            continue
+        H = sp.hamiltonian()
+        terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
+        part = ofac.first_fit(terms, job.budget, job.t / job.steps)
+        ref = oev.evolve(terms, part, r.psi0[0].astype(np.complex128), H.n, job.t / job.steps, job.steps)
+        worst = min(worst, float(metrics.fidelity(r.psi[0].astype(np.complex128), ref)))
+        checked += 1
+    st.update(jobs=n_jobs, rate_jobs_s=rate, oracle_sample=len(sample), oracle_checked=checked,
+              oracle_min_fidelity=worst, families="tfim/heisenberg/maxcut/tsp", n_range=[10, 24])
+    return st
+
+
+def summarize_profiles(trace_dir, fetch_dir, write_dir, command):
+    """Turn rocprofv3 CSV output of bench.py runs into the committed summaries:
+    per-kernel durations (trace) and per-launch HBM bytes of the DIA tile
+    kernel from FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each scaled by
+    what the same counter reads for the 2 GiB device copies the run makes."""
+    import csv
+    import glob
+
+    def rows(d, pattern):
+        out = []
+        for fn in glob.glob(os.path.join(d, "**", pattern), recursive=True):
+            with open(fn) as fh:
+                out += list(csv.DictReader(fh))
+        return out
+
+    stats = rows(trace_dir, "*kernel_stats.csv")
+    trace = sorted(rows(trace_dir, "*kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
+    tile = [r for r in trace if "dia_tile_kernel" in r["Kernel_Name"]]
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    md = ["# dia_tile_kernel on tfim2d 5x5 + ancilla, n=26, complex64, budget 16", "",
+          "Command (repository root, GPU box):", "", "```", command, "```", "",
+          "## rocprofv3 --kernel-trace --stats summary", "",
+          "| kernel | calls | avg us | min us | max us | % |", "|---|---|---|---|---|---|"]
+    for r in stats:
+        md.append(f"| {r['Name'][:70]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                  f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    # per-launch position within a step (launches repeat each step)
+    fetch = sorted(rows(fetch_dir, "*counter_collection.csv"), key=lambda r: int(r["Dispatch_Id"]))
+    write = sorted(rows(write_dir, "*counter_collection.csv"), key=lambda r: int(r["Dispatch_Id"]))
+
+    def copies(rs):
+        return [r for r in rs if "copyBuffer" in r["Kernel_Name"]]
+    wcopy = [float(r["Counter_Value"]) for r in copies(write)]
+    big = max(wcopy) if wcopy else 0.0
+    fcopy = [float(r["Counter_Value"]) for r in copies(fetch)]
+    expected_kib = (1 << 31) / 1024.0
+    f_scale = expected_kib / (sorted(fcopy)[-1] if fcopy else expected_kib)
+    w_scale = expected_kib / big if big else 1.0
+    ft = [float(r["Counter_Value"]) for r in fetch if "dia_tile_kernel" in r["Kernel_Name"]]
+    wt = [float(r["Counter_Value"]) for r in write if "dia_tile_kernel" in r["Kernel_Name"]]
+    nl = 3
+    per = []
+    for j in range(nl):
+        fk = ft[j::nl]
+        wk = wt[j::nl]
+        per.append(int((sum(fk) / len(fk) * f_scale + sum(wk) / len(wk) * w_scale) * 1024))
+    durs = [[] for _ in range(nl)]
+    for i, r in enumerate(tile):
+        durs[i % nl].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+    md += ["", "## HBM traffic of dia_tile_kernel per launch position in a step", "",
+           f"Copy calibration: a 2 GiB device copy reads {sorted(fcopy)[-1] if fcopy else 0:.0f} KiB "
+           f"(FETCH_SIZE) and writes {big:.0f} KiB (WRITE_SIZE); scale factors {f_scale:.4f} "
+           f"and {w_scale:.4f}.", "",
+           "| launch | avg ms | FETCH KiB | WRITE KiB | scaled GB |", "|---|---|---|---|---|"]
+    for j in range(nl):
+        md.append(f"| {j} | {sum(durs[j]) / max(1, len(durs[j])):.3f} | {sum(ft[j::nl]) / len(ft[j::nl]):.0f} | "
+                  f"{sum(wt[j::nl]) / len(wt[j::nl]):.0f} | {per[j] / 1e9:.3f} |")
+    with open(os.path.join(ROOT, "profiles", "dia_tile_tfim2d_n26.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump({"kernel_sha": kernel_hash(), "bytes_per_launch_scaled": per,
+                   "fetch_scale": f_scale, "write_scale": w_scale, "command": command}, fh, indent=1)
+    print("\n".join(md))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,7 +224,18 @@ def main():
     ap.add_argument("--renorm", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8, help="oracle sample size (0 = skip)")
     ap.add_argument("--no-copy-ref", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=300, help="served-stream size (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-oracle-nmax", type=int, default=16)
+    ap.add_argument("--serve-only", action="store_true", help="only the served stream")
+    ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
+                    help="write profiles/ summaries from rocprofv3 output directories")
+    ap.add_argument("--profile-command", default="")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(*args.summarize_profiles, args.profile_command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -133,6 +246,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.serve_only:
+        st = serve_leg(torch, args.serve_jobs, args.serve_rate, args.serve_slots, args.serve_oracle_nmax)
+        print(json.dumps({"metric": "served-solve latency", "serve": st}), flush=True)
+        return
     H = config_hamiltonian(3)
     N = 1 << H.n
     budget, t, steps_total = 16, 1.0, 50
@@ -178,8 +295,8 @@ def main():
     avg_launch_bytes = step_bytes / len(launches)
     achieved = avg_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(per_launch),
-            "kernel": "dia_tile_kernel<float,1,16,closed>",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(per_launch, len(launches)),
+            "kernel": "dia_tile_kernel (complex64, batch 1, closed tiles)",
             "algorithmic_bytes_per_launch": [int(b) for b in per_launch],
             "avg_launch_ms": round(avg_launch_ms, 4)}
 
@@ -198,6 +315,13 @@ def main():
         cpu = cpu_baseline(H, psi0, budget, t, steps_total, args.cpu_steps, step_bytes)
         log(f"oracle {cpu['ms_per_step']} ms/step ({cpu['cores']} threads)")
 
+    serve = None
+    if args.serve_jobs > 0:
+        f.close()
+        torch.cuda.empty_cache()
+        serve = serve_leg(torch, args.serve_jobs, args.serve_rate, args.serve_slots,
+                          args.serve_oracle_nmax)
+
     line = {
         "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -208,7 +332,7 @@ def main():
         "step_ms_median": round(float(np.median(step_ms)), 4),
         "step_ms_p90": round(float(np.percentile(step_ms, 90)), 4),
         "bytes_per_step": int(step_bytes), "build_s": round(build_s, 3),
-        "closure_ok": bool(closure_ok), **extra,
+        "closure_ok": bool(closure_ok), **extra, "serve": serve,
     }
     print(json.dumps(line), flush=True)
     f.close()

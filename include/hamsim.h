@@ -20,6 +20,7 @@
  *  - Diagonal d of an N x N operator holds A[r, r+d] at storage index
  *    min(r, r+d) and has N - |d| entries (Section 3.2, Eq. 6; element map of
  *    the DiagonalTimesVector schematic, Section 3.3).
+ *  - State and diagonal pointers must be 16-byte aligned (HS_EINVAL otherwise).
  *  - Device pointers are HIP device addresses on the current device; a
  *    stream argument is a hipStream_t (NULL = the default stream).  All device
  *    work is enqueued on that stream.
@@ -100,8 +101,9 @@ hs_status hs_plan(int n_qubits, int n_terms, const char *const *pauli_terms,
  * diagonal terms) when r and r+d agree outside the factor's support, else 0;
  * they are then stored as complex64 (dtype HS_C64, rounded to nearest) or
  * complex128.  Each diagonal starts on a 256-byte boundary.  The library owns
- * this memory until hs_free_factors.  The call synchronises `stream` before
- * returning.
+ * this memory until hs_free_factors.  Device memory is allocated and later
+ * released stream-ordered on `stream`, which must stay valid until
+ * hs_free_factors.  The call synchronises `stream` before returning.
  */
 hs_status hs_build_factors(int n_qubits, int n_terms, const char *const *pauli_terms,
                            const double *coeffs, double t, int steps, int budget,
@@ -150,6 +152,8 @@ hs_status hs_step_launches(hs_factors f, int batch, unsigned flags, int *n_launc
 /* Sets *violated to 1 if any in-place launch met a nonzero coefficient that
  * couples rows of different tiles (never for factors built here); syncs. */
 hs_status hs_check(hs_factors f, void *stream, int *violated);
+/* Release a handle.  Device memory is returned stream-ordered on the build
+ * stream; work that uses the factors on other streams must have completed. */
 hs_status hs_free_factors(hs_factors f);
 
 /*

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -54,16 +55,14 @@ struct Geo {
     bool ok = false;
 };
 
-// Largest tile (rows) the kernel holds: 16 complex64 / 8 complex128
-// accumulators per thread, shared by the batch rounded up to a power of two.
-int tile_rows_max(int dtype, int batch) {
-    int bp = 1;
-    while (bp < batch) bp <<= 1;
-    const int te = dtype == HS_C128 ? 8 : 16;
-    return 256 * std::max(1, te / bp);
-}
+// Largest tile (rows) one launch of `batch` states holds.
+int tile_rows_max(int dtype, int batch) { return hs::tile_rows_cap(dtype == HS_C128, batch); }
 
-int w_min(int dtype) { return dtype == HS_C128 ? 16 : 32; }   // 256-byte row runs
+#ifndef HS_TILE_WMIN_BYTES
+#define HS_TILE_WMIN_BYTES 256
+#endif
+// shortest run of consecutive rows a strided tile may have (bytes of one state)
+int w_min(int dtype) { return HS_TILE_WMIN_BYTES / (dtype == HS_C128 ? 16 : 8); }
 
 Geo geometry(int lb, int hb, int n, int Tmax) {
     Geo g;
@@ -109,19 +108,22 @@ struct hs_factors_s {
     int device = 0;
     int *viol_dev = nullptr;
     double *work_dev = nullptr;      // [8][G][4] partials, then [8][4] records
+    hipStream_t alloc_stream = nullptr;   // device memory is stream-ordered on this stream
     std::map<std::pair<int, int>, EvolvePlan> plans;   // (chunk batch, fuse)
     std::mutex mu;
 
     double *partials() { return work_dev; }
     double *records() { return work_dev + (size_t)HS_MAX_BATCH * hs::kReduceBlocks * 4; }
 
+    // Stream-ordered frees (hipFree would wait for the whole device, stalling
+    // other handles' work on other streams).
     ~hs_factors_s() {
         for (auto &f : plan.factors)
-            if (f.dev) (void)hipFree(f.dev);
+            if (f.dev) (void)hipFreeAsync(f.dev, alloc_stream);
         for (auto &kv : plans)
-            if (kv.second.dev_desc) (void)hipFree(kv.second.dev_desc);
-        if (viol_dev) (void)hipFree(viol_dev);
-        if (work_dev) (void)hipFree(work_dev);
+            if (kv.second.dev_desc) (void)hipFreeAsync(kv.second.dev_desc, alloc_stream);
+        if (viol_dev) (void)hipFreeAsync(viol_dev, alloc_stream);
+        if (work_dev) (void)hipFreeAsync(work_dev, alloc_stream);
     }
 };
 
@@ -194,12 +196,13 @@ hs_status make_evolve_plan(hs_factors_s *h, int batch, bool fuse, EvolvePlan &ep
         f = g;
     }
     const size_t bytes = ep.host_desc.size() * sizeof(DiagDesc);
-    HS_HIP(hipMalloc(&ep.dev_desc, std::max<size_t>(bytes, 64)), "hipMalloc(descriptors)");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    HS_HIP(hipMallocAsync(reinterpret_cast<void **>(&ep.dev_desc), std::max<size_t>(bytes, 64), st),
+           "hipMallocAsync(descriptors)");
     // the host table lives as long as the plan, so an ordered async copy is safe
-    hipError_t e = hipMemcpyAsync(ep.dev_desc, ep.host_desc.data(), bytes, hipMemcpyHostToDevice,
-                                  reinterpret_cast<hipStream_t>(stream));
+    hipError_t e = hipMemcpyAsync(ep.dev_desc, ep.host_desc.data(), bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) {
-        (void)hipFree(ep.dev_desc);
+        (void)hipFreeAsync(ep.dev_desc, st);
         ep.dev_desc = nullptr;
         return hip_fail(e, "hipMemcpy(descriptors)");
     }
@@ -277,25 +280,29 @@ static hs_status build_device(hs_factors_s *h, void *stream) {
     const size_t sc = elem_bytes(h->dtype);
     const bool c128 = h->dtype == HS_C128;
     HS_HIP(hipGetDevice(&h->device), "hipGetDevice");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    h->alloc_stream = st;
     for (auto &f : P.factors) {
         hs::layout_factor(f, P.N, sc);
-        HS_HIP(hipMalloc(&f.dev, f.elems_total * sc), "hipMalloc(factor diagonals)");
+        HS_HIP(hipMallocAsync(&f.dev, f.elems_total * sc, st), "hipMallocAsync(factor diagonals)");
     }
-    HS_HIP(hipMalloc(&h->viol_dev, sizeof(int)), "hipMalloc(flag)");
-    HS_HIP(hipMemset(h->viol_dev, 0, sizeof(int)), "hipMemset(flag)");
-    HS_HIP(hipMalloc(&h->work_dev, sizeof(double) * ((size_t)HS_MAX_BATCH * hs::kReduceBlocks * 4 + HS_MAX_BATCH * 4)),
-           "hipMalloc(workspace)");
+    HS_HIP(hipMallocAsync(reinterpret_cast<void **>(&h->viol_dev), sizeof(int), st), "hipMallocAsync(flag)");
+    HS_HIP(hipMemsetAsync(h->viol_dev, 0, sizeof(int), st), "hipMemsetAsync(flag)");
+    HS_HIP(hipMallocAsync(reinterpret_cast<void **>(&h->work_dev),
+                          sizeof(double) * ((size_t)HS_MAX_BATCH * hs::kReduceBlocks * 4 + HS_MAX_BATCH * 4), st),
+           "hipMallocAsync(workspace)");
 
     // temporaries: phase table and per-factor tables
     std::vector<void *> temps;
     auto cleanup = [&]() {
-        for (void *p : temps) (void)hipFree(p);
+        for (void *p : temps) (void)hipFreeAsync(p, st);
     };
     auto upload = [&](const void *src, size_t bytes, void **dst) -> hipError_t {
-        hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 16));
+        // host sources stay alive until the stream is synchronised below
+        hipError_t e = hipMallocAsync(dst, std::max<size_t>(bytes, 16), st);
         if (e != hipSuccess) return e;
         temps.push_back(*dst);
-        return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        return hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, st);
     };
     double *phase = nullptr;
     hipError_t e = hipSuccess;
@@ -309,7 +316,7 @@ static hs_status build_device(hs_factors_s *h, void *stream) {
         void *dzm = nullptr, *dcf = nullptr;
         if ((e = upload(zm.data(), zm.size() * 8, &dzm)) != hipSuccess ||
             (e = upload(cf.data(), cf.size() * 8, &dcf)) != hipSuccess ||
-            (e = hipMalloc(reinterpret_cast<void **>(&phase), (size_t)P.N * 16)) != hipSuccess) {
+            (e = hipMallocAsync(reinterpret_cast<void **>(&phase), (size_t)P.N * 16, st)) != hipSuccess) {
             cleanup();
             return hip_fail(e, "phase table setup");
         }
@@ -387,6 +394,7 @@ hs_status hs_evolve(hs_factors f, void *psi, int batch, int steps, void *stream,
     if (batch < 1) return fail(HS_EINVAL, "batch must be >= 1");
     if (steps < 0) return fail(HS_EINVAL, "steps must be >= 0");
     if (flags & ~(unsigned)(HS_RENORM | HS_NO_FUSE)) return fail(HS_EINVAL, "unknown evolve flag");
+    if (reinterpret_cast<uintptr_t>(psi) % 16) return fail(HS_EINVAL, "state pointer must be 16-byte aligned");
     if (steps == 0) return HS_OK;
     std::lock_guard<std::mutex> lock(f->mu);
     const Plan &P = f->plan;
@@ -515,9 +523,9 @@ hs_status hs_step_launches(hs_factors f, int batch, unsigned flags, int *n_launc
     auto it = f->plans.find(key);
     if (it == f->plans.end()) {
         EvolvePlan ep;
-        if (hs_status s = make_evolve_plan(f, chunk, fuse, ep, nullptr)) return s;
+        if (hs_status s = make_evolve_plan(f, chunk, fuse, ep, f->alloc_stream)) return s;
         it = f->plans.emplace(key, std::move(ep)).first;
-        HS_HIP(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
+        HS_HIP(hipStreamSynchronize(f->alloc_stream), "hipStreamSynchronize");
     }
     const auto &runs = it->second.runs;
     *n_launches = (int)runs.size();
@@ -579,12 +587,15 @@ hs_status hs_dia_spmv(int n_diags, const long long *offsets, const void *const *
     char *yb = static_cast<char *>(y);
     const size_t span = (size_t)batch * N * sc;
     if (xb < yb + span && yb < xb + span) return fail(HS_EINVAL, "x and y overlap");
+    if (reinterpret_cast<uintptr_t>(x) % 16 || reinterpret_cast<uintptr_t>(y) % 16)
+        return fail(HS_EINVAL, "x and y must be 16-byte aligned");
     uint64_t orall = 0;
     long long maxabs = 0;
     for (int j = 0; j < n_diags; ++j) {
         if (offsets[j] <= -N || offsets[j] >= N) return fail(HS_EINVAL, "offset out of range");
         if (j && offsets[j] <= offsets[j - 1]) return fail(HS_EINVAL, "offsets must ascend strictly");
         if (!diags[j]) return fail(HS_EINVAL, "null diagonal pointer");
+        if (reinterpret_cast<uintptr_t>(diags[j]) % 16) return fail(HS_EINVAL, "diagonals must be 16-byte aligned");
         const long long a = offsets[j] < 0 ? -offsets[j] : offsets[j];
         orall |= (uint64_t)a;
         maxabs = std::max(maxabs, a);
@@ -621,8 +632,9 @@ hs_status hs_dia_spmv(int n_diags, const long long *offsets, const void *const *
             dd.hi = (int32_t)std::min<long long>(N, N - d);
         }
         DiagDesc *ddev = nullptr;
-        HS_HIP(hipMalloc(&ddev, sizeof(DiagDesc) * n_diags), "hipMalloc(descriptors)");
         hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+        HS_HIP(hipMallocAsync(reinterpret_cast<void **>(&ddev), sizeof(DiagDesc) * n_diags, st),
+               "hipMallocAsync(descriptors)");
         hipError_t e = hipMemcpyAsync(ddev, hd.data(), sizeof(DiagDesc) * n_diags, hipMemcpyHostToDevice, st);
         TileArgs a{};
         a.y = yb + (size_t)c0 * N * sc;
@@ -641,7 +653,7 @@ hs_status hs_dia_spmv(int n_diags, const long long *offsets, const void *const *
             e = (hipError_t)le;
         }
         hipError_t e2 = hipStreamSynchronize(st);
-        (void)hipFree(ddev);
+        (void)hipFreeAsync(ddev, st);
         if (e != hipSuccess) return hip_fail(e, "dia_spmv launch");
         if (e2 != hipSuccess) return hip_fail(e2, "dia_spmv");
     }
@@ -652,15 +664,16 @@ static hs_status reduce_call(const void *A, int ta, const void *B, int tb, int b
                              void *stream, bool dot, std::vector<double> &rec) {
     const int G = hs::kReduceBlocks;
     double *work = nullptr;
-    HS_HIP(hipMalloc(&work, sizeof(double) * ((size_t)batch * G * 4 + (size_t)batch * 4)), "hipMalloc(reduce)");
-    double *out = work + (size_t)batch * G * 4;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    HS_HIP(hipMallocAsync(reinterpret_cast<void **>(&work), sizeof(double) * ((size_t)batch * G * 4 + (size_t)batch * 4), st),
+           "hipMallocAsync(reduce)");
+    double *out = work + (size_t)batch * G * 4;
     int le = hs::launch_reduce(A, ta, B, tb, batch, N, work, G, out, dot, stream);
     rec.assign((size_t)batch * 4, 0.0);
     hipError_t e = (hipError_t)le;
     if (e == hipSuccess) e = hipMemcpyAsync(rec.data(), out, sizeof(double) * batch * 4, hipMemcpyDeviceToHost, st);
     hipError_t e2 = hipStreamSynchronize(st);
-    (void)hipFree(work);
+    (void)hipFreeAsync(work, st);
     if (e != hipSuccess) return hip_fail(e, "reduction");
     if (e2 != hipSuccess) return hip_fail(e2, "reduction");
     return HS_OK;

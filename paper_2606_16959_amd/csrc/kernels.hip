@@ -116,12 +116,101 @@ __global__ void construct_kernel(ConstructArgs a) {
 // exactly once, by the thread that owns its row, along the diagonal in
 // consecutive addresses.
 //
+// A thread owns pairs of adjacent rows (local indices i, i+1 with i even;
+// W is 1 or even, so the two rows are adjacent in the state too).  For an
+// even offset the two coefficients are adjacent and 16-byte aligned
+// (diagonals start on 256-byte boundaries), so complex64 pairs are fetched
+// with one 16-byte load; odd offsets use two 8-byte loads.  Loads are issued
+// for all pairs of a diagonal before any is consumed, with clamped indices and
+// masks instead of branches, so a wave keeps many loads in flight.
+//
 // Closed launches (factors built by this library, whose nonzeros only couple
 // rows inside one tile) run in place and do not read outside the tile: a
 // nonzero out-of-tile coefficient only raises the violation flag.  A fused
 // launch applies several factors in turn on the tile held in LDS.
+
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) f2v g_f2;
+typedef const __attribute__((address_space(1))) f4v g_f4;
+typedef const __attribute__((address_space(1))) d2v g_d2;
+
+#ifndef HS_TILE_NT
+#define HS_TILE_NT 1          // streaming (non-temporal) hint on coefficient and state loads
+#endif
+#if HS_TILE_NT
+#define HS_LOAD(ptr) __builtin_nontemporal_load(ptr)
+#else
+#define HS_LOAD(ptr) (*(ptr))
+#endif
+
+__device__ __forceinline__ C2<float> ld1(const C2<float> *p, int i) {
+    const f2v v = HS_LOAD((g_f2 *)(p) + i);
+    return C2<float>{v.x, v.y};
+}
+__device__ __forceinline__ C2<double> ld1(const C2<double> *p, int i) {
+    const d2v v = HS_LOAD((g_d2 *)(p) + i);
+    return C2<double>{v.x, v.y};
+}
+// entries i and i+1 (i even)
+__device__ __forceinline__ void ld2(const C2<float> *p, int i, C2<float> &a, C2<float> &b) {
+    const f4v v = HS_LOAD((g_f4 *)(p) + (i >> 1));
+    a = C2<float>{v.x, v.y};
+    b = C2<float>{v.z, v.w};
+}
+__device__ __forceinline__ void ld2(const C2<double> *p, int i, C2<double> &a, C2<double> &b) {
+    a = ld1(p, i);
+    b = ld1(p, i + 1);
+}
+
+template <typename R>
+__device__ __forceinline__ C2<R> cmask(C2<R> c, bool keep) {
+    return keep ? c : C2<R>{(R)0, (R)0};
+}
+
+#ifndef HS_TILE_PREFETCH
+#define HS_TILE_PREFETCH 0     // 1: load the next diagonal's coefficients before using this one's
+#endif
+
+// Coefficients of one diagonal for every row pair a thread owns (masked
+// loads: invalid rows read entry 0 and are zeroed when consumed).
+template <typename R, int P, int NT>
+__device__ __forceinline__ void load_diag(C2<R> (&c)[P][2], const DiagDesc &dd, int tid, int T,
+                                          int base, int qb, int logW) {
+    const C2<R> *cp = reinterpret_cast<const C2<R> *>(dd.ptr);
+    const int neg = dd.off < 0 ? dd.off : 0;
+    const int len = dd.hi - dd.lo;            // N - |d| entries
+    const int W = 1 << logW;
+    if ((dd.off & 1) == 0) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+            const int r0 = base + ((i0 >> logW) << qb) + (i0 & (W - 1));
+            int e = r0 + neg;
+            e = (e >= 0 && e < len && i0 < T) ? e : 0;   // even d: pairs never straddle lo/hi
+            ld2(cp, e, c[p][0], c[p][1]);
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+            const int r0 = base + ((i0 >> logW) << qb) + (i0 & (W - 1));
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                int e = r0 + k + neg;
+                e = (e >= 0 && e < len && i0 < T) ? e : 0;
+                c[p][k] = ld1(cp, e);
+            }
+        }
+    }
+}
+
 template <typename R, int B, int RPT, bool CLOSED>
-__global__ __launch_bounds__(256) void dia_tile_kernel(TileArgs a) {
+__global__ __launch_bounds__(kTileThreads) void dia_tile_kernel(TileArgs a) {
+    static_assert(RPT % 2 == 0, "rows come in pairs");
+    constexpr int P = RPT / 2;
+    constexpr int NT = kTileThreads;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<R> *lds = reinterpret_cast<C2<R> *>(smem_raw);
     const int T = a.T;
@@ -129,7 +218,15 @@ __global__ __launch_bounds__(256) void dia_tile_kernel(TileArgs a) {
     const int qb = a.qb, kb = a.kb, logW = a.logW;
     const int W = 1 << logW;
     const int L = 1 << kb;
-    const int blk = blockIdx.x;
+#ifndef HS_TILE_XCD_SWIZZLE
+#define HS_TILE_XCD_SWIZZLE 0
+#endif
+    int blk = blockIdx.x;
+    if (HS_TILE_XCD_SWIZZLE && (gridDim.x & 7) == 0) {
+        // workgroups are dealt to the 8 XCDs round-robin: give each XCD one
+        // contiguous eighth of the tiles
+        blk = (blk & 7) * (gridDim.x >> 3) + (blk >> 3);
+    }
     const int hi = blk >> a.nlw_log;
     const int lw = blk & ((1 << a.nlw_log) - 1);
     const int base = (hi << (qb + kb)) | (lw << logW);
@@ -140,81 +237,125 @@ __global__ __launch_bounds__(256) void dia_tile_kernel(TileArgs a) {
 #pragma unroll
     for (int b = 0; b < B; ++b) scale[b] = inv_norm<R>(a.nrm2, b);
 
-    // stage the tile
+    // local index of pair p: i0 = 2*tid + 2*NT*p (and i0 + 1)
+    auto row_of = [&](int i) { return base + ((i >> logW) << qb) + (i & (W - 1)); };
+
+    // stage the tile: issue every load, then write LDS
+    {
+        C2<R> u[P][2][B];
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int i = tid + j * 256;
-        if (i < T) {
-            const int r = base + ((i >> logW) << qb) + (i & (W - 1));
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+            const int r0 = i0 < T ? row_of(i0) : base;
 #pragma unroll
-            for (int b = 0; b < B; ++b) lds[b * T + i] = cscale(x[b * a.stride + r], scale[b]);
+            for (int b = 0; b < B; ++b) ld2(x + b * a.stride, r0, u[p][0][b], u[p][1][b]);
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+            if (i0 < T)
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    lds[b * T + i0] = cscale(u[p][0][b], scale[b]);
+                    lds[b * T + i0 + 1] = cscale(u[p][1][b], scale[b]);
+                }
         }
     }
+
+    const int total = a.dstart[a.nf];
+    C2<R> c[P][2];
+    load_diag<R, P, NT>(c, a.desc[0], tid, T, base, qb, logW);
     __syncthreads();
 
-    C2<R> acc[RPT][B];
+    C2<R> acc[P][2][B];
     bool viol = false;
+    int dj = 0;
     for (int f = 0; f < a.nf; ++f) {
 #pragma unroll
-        for (int j = 0; j < RPT; ++j)
+        for (int p = 0; p < P; ++p)
 #pragma unroll
-            for (int b = 0; b < B; ++b) acc[j][b] = C2<R>{(R)0, (R)0};
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int b = 0; b < B; ++b) acc[p][k][b] = C2<R>{(R)0, (R)0};
 
-        for (int dj = a.dstart[f]; dj < a.dstart[f + 1]; ++dj) {
+        for (; dj < a.dstart[f + 1]; ++dj) {
             const DiagDesc dd = a.desc[dj];
-            const C2<R> *__restrict__ cp = reinterpret_cast<const C2<R> *>(dd.ptr);
-            const int neg = dd.off < 0 ? dd.off : 0;
+            C2<R> cn[P][2];
+            if (HS_TILE_PREFETCH && dj + 1 < total) load_diag<R, P, NT>(cn, a.desc[dj + 1], tid, T, base, qb, logW);
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) {
-                const int i = tid + j * 256;
-                if (i >= T) continue;
-                const int r = base + ((i >> logW) << qb) + (i & (W - 1));
-                if (r < dd.lo || r >= dd.hi) continue;       // no entry on this diagonal
-                bool in;
-                int loc;
-                const int p = r + dd.off;
-                if (dd.regular) {
-                    const int lvl = (i >> logW) + dd.m;
-                    in = (unsigned)lvl < (unsigned)L;
-                    loc = i + dd.m * W;
-                } else {
-                    in = (p >> (qb + kb)) == hi && ((p & ((1 << qb) - 1)) >> logW) == lw;
-                    loc = (((p >> qb) & (L - 1)) << logW) | (p & (W - 1));
-                }
-                const C2<R> c = cp[r + neg];
-                if (in) {
+            for (int p = 0; p < P; ++p) {
+                const int i0 = 2 * tid + 2 * NT * p;
+                const int r0 = row_of(i0);
 #pragma unroll
-                    for (int b = 0; b < B; ++b) cfma(acc[j][b], c, lds[b * T + loc]);
-                } else if (c.re != (R)0 || c.im != (R)0) {
-                    if (CLOSED) {
-                        viol = true;
+                for (int k = 0; k < 2; ++k) {
+                    const int i = i0 + k;
+                    const int r = r0 + k;
+                    const bool valid = i0 < T && r >= dd.lo && r < dd.hi;
+                    const C2<R> cv = cmask(c[p][k], valid);
+                    bool in;
+                    int loc;
+                    if (dd.regular) {
+                        const int lvl = (i >> logW) + dd.m;
+                        in = (unsigned)lvl < (unsigned)L;
+                        loc = i + dd.m * W;
                     } else {
-#pragma unroll
-                        for (int b = 0; b < B; ++b) cfma(acc[j][b], c, cscale(x[b * a.stride + p], scale[b]));
+                        const int pr = r + dd.off;
+                        in = (pr >> (qb + kb)) == hi && ((pr & ((1 << qb) - 1)) >> logW) == lw;
+                        loc = (((pr >> qb) & (L - 1)) << logW) | (pr & (W - 1));
                     }
+                    const bool nz = cv.re != (R)0 || cv.im != (R)0;
+                    const int sl = in ? loc : (i < T ? i : 0);
+                    const C2<R> ce = cmask(cv, in);
+#pragma unroll
+                    for (int b = 0; b < B; ++b) cfma(acc[p][k][b], ce, lds[b * T + sl]);
+                    if (!in && nz) {
+                        if (CLOSED) {
+                            viol = true;
+                        } else {
+                            const int pr = r + dd.off;
+#pragma unroll
+                            for (int b = 0; b < B; ++b)
+                                cfma(acc[p][k][b], cv, cscale(x[b * a.stride + pr], scale[b]));
+                        }
+                    }
+                }
+            }
+            if (!HS_TILE_PREFETCH && dj + 1 < total) {
+                load_diag<R, P, NT>(c, a.desc[dj + 1], tid, T, base, qb, logW);
+            } else {
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    c[p][0] = cn[p][0];
+                    c[p][1] = cn[p][1];
                 }
             }
         }
         if (f + 1 < a.nf) {
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) {
-                const int i = tid + j * 256;
-                if (i < T)
+            for (int p = 0; p < P; ++p) {
+                const int i0 = 2 * tid + 2 * NT * p;
+                if (i0 < T)
 #pragma unroll
-                    for (int b = 0; b < B; ++b) lds[b * T + i] = acc[j][b];
+                    for (int b = 0; b < B; ++b) {
+                        lds[b * T + i0] = acc[p][0][b];
+                        lds[b * T + i0 + 1] = acc[p][1][b];
+                    }
             }
             __syncthreads();
         }
     }
 
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int i = tid + j * 256;
-        if (i < T) {
-            const int r = base + ((i >> logW) << qb) + (i & (W - 1));
+    for (int p = 0; p < P; ++p) {
+        const int i0 = 2 * tid + 2 * NT * p;
+        if (i0 < T) {
+            const int r0 = row_of(i0);
 #pragma unroll
-            for (int b = 0; b < B; ++b) y[b * a.stride + r] = acc[j][b];
+            for (int b = 0; b < B; ++b) {
+                y[b * a.stride + r0] = acc[p][0][b];
+                y[b * a.stride + r0 + 1] = acc[p][1][b];
+            }
         }
     }
     if (CLOSED && viol) atomicOr(a.viol, 1);
@@ -339,30 +480,28 @@ int launch_construct(const ConstructArgs &a, int nd, int64_t max_len, bool c128,
     return (int)hipGetLastError();
 }
 
-template <typename R, int B, int RPT>
-static void tile_dispatch_closed(const TileArgs &a, bool closed, void *stream) {
+template <typename R, int B>
+static void tile_dispatch_b(const TileArgs &a, bool closed, void *stream) {
+    constexpr int RPT = tile_rpt(sizeof(R) == 8, B);
     const size_t lds = (size_t)a.T * B * sizeof(C2<R>);
     const int grid = (int)(a.N / a.T);
     if (closed)
-        hipLaunchKernelGGL((dia_tile_kernel<R, B, RPT, true>), dim3(grid), dim3(256), lds, S(stream), a);
+        hipLaunchKernelGGL((dia_tile_kernel<R, B, RPT, true>), dim3(grid), dim3(kTileThreads), lds, S(stream), a);
     else
-        hipLaunchKernelGGL((dia_tile_kernel<R, B, RPT, false>), dim3(grid), dim3(256), lds, S(stream), a);
+        hipLaunchKernelGGL((dia_tile_kernel<R, B, RPT, false>), dim3(grid), dim3(kTileThreads), lds, S(stream), a);
 }
 
-// rows per thread: 16 (complex64) or 8 (complex128) accumulators per thread,
-// split over the batch rounded up to a power of two.
 template <typename R>
 static int tile_dispatch(const TileArgs &a, int batch, bool closed, void *stream) {
-    constexpr int TE = sizeof(R) == 4 ? 16 : 8;
     switch (batch) {
-        case 1: tile_dispatch_closed<R, 1, TE>(a, closed, stream); break;
-        case 2: tile_dispatch_closed<R, 2, TE / 2>(a, closed, stream); break;
-        case 3: tile_dispatch_closed<R, 3, TE / 4>(a, closed, stream); break;
-        case 4: tile_dispatch_closed<R, 4, TE / 4>(a, closed, stream); break;
-        case 5: tile_dispatch_closed<R, 5, (TE / 8 > 0 ? TE / 8 : 1)>(a, closed, stream); break;
-        case 6: tile_dispatch_closed<R, 6, (TE / 8 > 0 ? TE / 8 : 1)>(a, closed, stream); break;
-        case 7: tile_dispatch_closed<R, 7, (TE / 8 > 0 ? TE / 8 : 1)>(a, closed, stream); break;
-        case 8: tile_dispatch_closed<R, 8, (TE / 8 > 0 ? TE / 8 : 1)>(a, closed, stream); break;
+        case 1: tile_dispatch_b<R, 1>(a, closed, stream); break;
+        case 2: tile_dispatch_b<R, 2>(a, closed, stream); break;
+        case 3: tile_dispatch_b<R, 3>(a, closed, stream); break;
+        case 4: tile_dispatch_b<R, 4>(a, closed, stream); break;
+        case 5: tile_dispatch_b<R, 5>(a, closed, stream); break;
+        case 6: tile_dispatch_b<R, 6>(a, closed, stream); break;
+        case 7: tile_dispatch_b<R, 7>(a, closed, stream); break;
+        case 8: tile_dispatch_b<R, 8>(a, closed, stream); break;
         default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();

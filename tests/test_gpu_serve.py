@@ -1,0 +1,69 @@
+"""Served loop on the GPU: each job's result is the same alone and in the mix
+(bit for bit: same kernels, same launch shapes), results match the oracle,
+admission respects a tight HBM budget, and a failing job stays isolated."""
+import numpy as np
+import pytest
+
+from gpu_common import fid, hs_gpu, note, oracle_run
+from workloads.serve_stream import job_stream
+
+pytestmark = pytest.mark.gpu
+
+
+def _jobs(k=10, n_max=14, keep=True, seed=5):
+    from paper_2606_16959_amd.serve import Job
+    out = []
+    for spec in job_stream(n_jobs=k, rate=200.0, seed=seed, n_min=10, n_max=n_max):
+        H = spec.hamiltonian()
+        out.append((spec, Job(spec.job_id, H.strings, H.coeffs, H.n, spec.t, spec.steps, spec.batch,
+                                spec.state_seed, arrival=spec.arrival, keep_result=keep,
+                                tag=spec.family)))
+    return out
+
+
+def test_alone_equals_mixed_bitwise_and_matches_oracle():
+    hs, torch = hs_gpu()
+    from paper_2606_16959_amd.serve import Server
+    pairs = _jobs(10)
+    jobs = [j for _, j in pairs]
+    note("serve: 10 jobs mixed on 4 slots")
+    mixed, st = Server(slots=4).run(jobs)
+    assert st["completed"] == 10, [r.error for r in mixed]
+    assert st["peak_active"] >= 2
+    note("serve: the same jobs one at a time")
+    for j, rm in zip(jobs, mixed):
+        alone, _ = Server(slots=1).run([j], realtime=False)
+        ra = alone[0]
+        assert ra.status == "ok"
+        assert np.array_equal(ra.psi0, rm.psi0)
+        assert np.array_equal(ra.psi, rm.psi), j.job_id
+    note("serve: oracle check of the mixed results")
+    for (spec, j), r in zip(pairs, mixed):
+        ref = oracle_run(spec.hamiltonian(), j.budget, j.t, j.steps, r.psi0.astype(np.complex128))
+        assert np.all(fid(r.psi.astype(np.complex128), ref) >= 1 - 1e-6), (spec.family, spec.n)
+        assert np.all(np.abs(r.norm2 - 1.0) < 1e-4)
+
+
+def test_tight_budget_serialises_but_completes():
+    hs, torch = hs_gpu()
+    from paper_2606_16959_amd.serve import Server
+    jobs = [j for _, j in _jobs(8, n_max=16, keep=False, seed=7)]
+    s = Server(slots=4)
+    fps = [s.footprint(j) for j in jobs]
+    s.hbm_budget = max(fps) + min(fps)          # at most two jobs' worth
+    note("serve: tight HBM budget")
+    res, st = s.run(jobs)
+    assert st["completed"] == 8
+    assert st["peak_hbm_bytes"] <= s.hbm_budget
+
+
+def test_failing_job_is_isolated():
+    hs, torch = hs_gpu()
+    from paper_2606_16959_amd.serve import Job, Server
+    jobs = [j for _, j in _jobs(3, keep=False)]
+    bad = Job(99, ["XXX"], np.array([1.0]), 3, 1.0, 5, 1, 0, budget=4, arrival=0.0)   # over budget
+    note("serve: one failing job among good ones")
+    res, st = Server(slots=2).run(jobs + [bad])
+    status = {r.job_id: r.status for r in res}
+    assert status[99] in ("error", "rejected")
+    assert all(status[j.job_id] == "ok" for j in jobs)

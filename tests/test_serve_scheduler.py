@@ -1,0 +1,89 @@
+"""Admission logic of the served loop, exercised on the CPU with a test double
+in place of the GPU job runner (same scheduler code, fake job execution)."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2606_16959_amd.serve import Job, Server, summarize
+
+
+class FakeServer(Server):
+    """Runs jobs by sleeping; footprint = declared size; records concurrency."""
+
+    def __init__(self, sizes, durations, **kw):
+        super().__init__(**kw)
+        self.sizes, self.durations = sizes, durations
+        self.lock = threading.Lock()
+        self.live = {}
+        self.max_used = 0
+        self.order = []
+
+    def footprint(self, job):
+        return self.sizes[job.job_id]
+
+    def _run_job(self, job, res, t0):
+        with self.lock:
+            self.live[job.job_id] = self.sizes[job.job_id]
+            self.max_used = max(self.max_used, sum(self.live.values()))
+            self.order.append(job.job_id)
+        res.start = time.perf_counter() - t0
+        time.sleep(self.durations[job.job_id])
+        res.end = time.perf_counter() - t0
+        with self.lock:
+            del self.live[job.job_id]
+        return res
+
+
+def _jobs(k, gap=0.0):
+    return [Job(j, ["X"], np.array([1.0]), 1, 1.0, 1, 1, 0, arrival=j * gap) for j in range(k)]
+
+
+def test_fifo_when_everything_fits():
+    s = FakeServer({j: 1 for j in range(8)}, {j: 0.01 for j in range(8)}, slots=2, hbm_budget=10)
+    res, st = s.run(_jobs(8, 0.001))
+    assert st["completed"] == 8 and s.order == list(range(8))
+    assert all(r.admit >= r.arrival - 1e-9 and r.end >= r.admit for r in res)
+    assert st["peak_active"] <= 2
+
+
+def test_hbm_budget_is_never_exceeded():
+    rng = np.random.default_rng(0)
+    sizes = {j: int(rng.integers(1, 7)) for j in range(30)}
+    s = FakeServer(sizes, {j: 0.005 for j in range(30)}, slots=4, hbm_budget=8)
+    res, st = s.run(_jobs(30, 0.0005))
+    assert st["completed"] == 30
+    assert s.max_used <= 8 and st["peak_hbm_bytes"] <= 8
+
+
+def test_bypass_is_bounded_and_big_job_finishes():
+    # job 1 needs the whole budget while small jobs keep arriving
+    sizes = {j: 1 for j in range(20)}
+    sizes[1] = 10
+    durations = {j: 0.02 for j in range(20)}
+    s = FakeServer(sizes, durations, slots=3, hbm_budget=10, bypass_limit=3)
+    res, st = s.run(_jobs(20, 0.002))
+    assert st["completed"] == 20
+    r1 = res[1]
+    assert r1.bypassed <= 3
+    # once its bypass budget is spent, job 1 starts before every job that was behind it
+    later = [r for r in res if r.job_id > 1 and r.admit > r1.admit]
+    assert len(later) >= 20 - 2 - 3 - 1
+
+
+def test_oversize_job_is_rejected_others_complete():
+    sizes = {0: 1, 1: 99, 2: 1}
+    s = FakeServer(sizes, {j: 0.001 for j in range(3)}, slots=2, hbm_budget=10)
+    res, st = s.run(_jobs(3))
+    assert [r.status for r in res] == ["ok", "rejected", "ok"]
+    assert st["completed"] == 2 and st["failed"] == 1
+
+
+def test_summary_fields():
+    s = FakeServer({j: 1 for j in range(5)}, {j: 0.002 for j in range(5)}, slots=2, hbm_budget=4)
+    res, st = s.run(_jobs(5, 0.001))
+    for key in ("latency_ms", "queue_wait_ms", "service_ms", "throughput_jobs_s", "gpu_busy_frac"):
+        assert key in st
+    assert st["latency_ms"]["p99"] >= st["latency_ms"]["p50"] > 0
+    assert summarize([])["completed"] == 0
