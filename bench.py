@@ -215,6 +215,89 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, command):
     print("\n".join(md))
 
 
+SWEEP = [
+    ("default", {}),
+    ("no_xcd_swizzle", {"HAMSIM_XCD_SWIZZLE": "0"}),
+    ("wmin512", {"HAMSIM_WMIN_BYTES": "512"}),
+    ("wmin512_no_swizzle", {"HAMSIM_WMIN_BYTES": "512", "HAMSIM_XCD_SWIZZLE": "0"}),
+    ("wmin1024", {"HAMSIM_WMIN_BYTES": "1024"}),
+    ("fuse1", {"HAMSIM_MAX_FUSE": "1"}),
+    ("fuse3", {"HAMSIM_MAX_FUSE": "3"}),
+]
+
+
+def sweep(torch, steps, warmup, rounds=3):
+    """Launch-plan variants of the same workload (environment knobs of the
+    library; one handle keeps a plan per setting), timed in interleaved rounds
+    (median); writes a summary under profiles/."""
+    import paper_2606_16959_amd as hs
+    from workloads import config_hamiltonian, states as ws
+    H = config_hamiltonian(3)
+    N = 1 << H.n
+    psi0 = ws.random_phase_state(H.n, 3, np.complex64)
+    f = hs.build_factors(H.strings, H.coeffs, H.n, 1.0, 50, 16, dtype="c64")
+    desc = f.describe()
+
+    def with_env(env, fn):
+        saved = {k: os.environ.get(k) for k in env}
+        os.environ.update(env)
+        try:
+            return fn()
+        finally:
+            for k, v in saved.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+
+    variants = []
+    for name, env in SWEEP:
+        launches = with_env(env, lambda: f.step_launches(1))   # the plan for this setting
+        per = launch_bytes(desc, launches, N, 1, 8)
+        variants.append({"name": name, "env": env, "launches": len(launches),
+                         "bytes": sum(per), "ms": []})
+    psi = torch.from_numpy(psi0).cuda()
+    ref = None
+    for rnd in range(rounds):
+        for v in variants:
+            psi.copy_(torch.from_numpy(psi0).cuda())
+
+            def run():
+                for _ in range(warmup):
+                    hs.evolve(f, psi, 1)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(steps):
+                    hs.evolve(f, psi, 1)
+                e1.record()
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) / steps
+            v["ms"].append(with_env(v["env"], run))
+            if rnd == 0:
+                out = psi.cpu().numpy()
+                v["same"] = bool(ref is None or np.array_equal(out, ref))
+                ref = out if ref is None else ref
+        log(f"sweep round {rnd} done")
+    md = ["# Launch-plan sweep: dia_tile_kernel, tfim2d 5x5 + ancilla, n=26, complex64", "",
+          "Command (repository root, GPU box): `python3 bench.py --sweep`", "",
+          f"Per variant: {warmup} warm-up + {steps} timed steps, repeated in {rounds} interleaved "
+          "rounds; median ms/step. Every variant's state after the first round is compared bit for "
+          "bit with the first variant's.", "",
+          "| variant | environment | launches/step | GB/step | ms/step (median) | min..max | GB/s | % of 8 TB/s | same result |",
+          "|---|---|---|---|---|---|---|---|---|"]
+    for v in variants:
+        ms = float(np.median(v["ms"]))
+        gbs = v["bytes"] / ms / 1e6
+        envs = " ".join(f"{k}={x}" for k, x in v["env"].items()) or "-"
+        md.append(f"| {v['name']} | {envs} | {v['launches']} | {v['bytes'] / 1e9:.2f} | {ms:.3f} | "
+                  f"{min(v['ms']):.3f}..{max(v['ms']):.3f} | {gbs:.1f} | {100 * gbs / HBM_PEAK_GBS:.1f} | {v['same']} |")
+    f.close()
+    with open(os.path.join(ROOT, "profiles", "sweep_launch_plan_tfim2d_n26.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +315,7 @@ def main():
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
                     help="write profiles/ summaries from rocprofv3 output directories")
     ap.add_argument("--profile-command", default="")
+    ap.add_argument("--sweep", action="store_true", help="launch-plan variants (writes profiles/)")
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(*args.summarize_profiles, args.profile_command)
@@ -246,6 +330,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.sweep:
+        sweep(torch, args.steps, args.warmup)
+        return
     if args.serve_only:
         st = serve_leg(torch, args.serve_jobs, args.serve_rate, args.serve_slots, args.serve_oracle_nmax)
         print(json.dumps({"metric": "served-solve latency", "serve": st}), flush=True)

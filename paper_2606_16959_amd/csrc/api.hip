@@ -7,11 +7,13 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "hs_internal.h"
@@ -58,11 +60,32 @@ struct Geo {
 // Largest tile (rows) one launch of `batch` states holds.
 int tile_rows_max(int dtype, int batch) { return hs::tile_rows_cap(dtype == HS_C128, batch); }
 
-#ifndef HS_TILE_WMIN_BYTES
-#define HS_TILE_WMIN_BYTES 256
-#endif
-// shortest run of consecutive rows a strided tile may have (bytes of one state)
-int w_min(int dtype) { return HS_TILE_WMIN_BYTES / (dtype == HS_C128 ? 16 : 8); }
+// Launch-plan tuning knobs, read from the environment at every evolve (a
+// handle keeps one plan per batch size and knob setting): HAMSIM_WMIN_BYTES (shortest run of consecutive rows a
+// strided tile may have, default 256), HAMSIM_MAX_FUSE (factors per launch,
+// default 8), HAMSIM_XCD_SWIZZLE (0/1, default 1: each XCD gets one
+// contiguous eighth of the tiles instead of every eighth tile).
+int env_int(const char *name, int dflt, int lo, int hi) {
+    const char *v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    char *end = nullptr;
+    long x = std::strtol(v, &end, 10);
+    if (end == v) return dflt;
+    return (int)std::min<long>(hi, std::max<long>(lo, x));
+}
+struct PlanKey {
+    int chunk, fuse, wmin_bytes, max_fuse, swizzle;
+    bool operator<(const PlanKey &o) const {
+        return std::tie(chunk, fuse, wmin_bytes, max_fuse, swizzle) <
+               std::tie(o.chunk, o.fuse, o.wmin_bytes, o.max_fuse, o.swizzle);
+    }
+};
+PlanKey plan_key(int chunk, bool fuse) {
+    return PlanKey{chunk, fuse ? 1 : 0, env_int("HAMSIM_WMIN_BYTES", 256, 8, 1 << 20),
+                   env_int("HAMSIM_MAX_FUSE", hs::kMaxRun, 1, hs::kMaxRun),
+                   env_int("HAMSIM_XCD_SWIZZLE", 1, 0, 1)};
+}
+int w_min(int dtype, const PlanKey &k) { return std::max(1, k.wmin_bytes / (dtype == HS_C128 ? 16 : 8)); }
 
 Geo geometry(int lb, int hb, int n, int Tmax) {
     Geo g;
@@ -94,6 +117,7 @@ struct Run {
 };
 
 struct EvolvePlan {
+    int swizzle = 0;
     std::vector<Run> runs;
     std::vector<DiagDesc> host_desc;
     DiagDesc *dev_desc = nullptr;
@@ -109,7 +133,7 @@ struct hs_factors_s {
     int *viol_dev = nullptr;
     double *work_dev = nullptr;      // [8][G][4] partials, then [8][4] records
     hipStream_t alloc_stream = nullptr;   // device memory is stream-ordered on this stream
-    std::map<std::pair<int, int>, EvolvePlan> plans;   // (chunk batch, fuse)
+    std::map<PlanKey, EvolvePlan> plans;
     std::mutex mu;
 
     double *partials() { return work_dev; }
@@ -131,13 +155,17 @@ namespace {
 
 // Greedy fusion: extend a run while the union of coupling hulls still fits
 // one closed tile with rows runs of at least w_min elements.
-hs_status make_evolve_plan(hs_factors_s *h, int batch, bool fuse, EvolvePlan &ep, void *stream) {
+hs_status make_evolve_plan(hs_factors_s *h, const PlanKey &key, EvolvePlan &ep, void *stream) {
     const Plan &P = h->plan;
     const int n = P.n;
+    const int batch = key.chunk;
+    const bool fuse = key.fuse != 0;
     const int Tmax = tile_rows_max(h->dtype, batch);
-    const int Wmin = w_min(h->dtype);
+    const int Wmin = w_min(h->dtype, key);
     const size_t sc = elem_bytes(h->dtype);
     ep = EvolvePlan();
+    ep.swizzle = key.swizzle;
+    const int max_fuse = key.max_fuse;
     const int F = (int)P.factors.size();
     int f = 0;
     while (f < F) {
@@ -150,7 +178,7 @@ hs_status make_evolve_plan(hs_factors_s *h, int batch, bool fuse, EvolvePlan &ep
         }
         int ndiag = (int)P.factors[f].offs.size();
         int g = f + 1;
-        while (fuse && g < F && (int)run.factors.size() < hs::kMaxRun) {
+        while (fuse && g < F && (int)run.factors.size() < max_fuse) {
             const Factor &G = P.factors[g];
             int nlb = lb, nhb = hb;
             if (G.xmask_union) {
@@ -238,6 +266,7 @@ hs_status launch_run(hs_factors_s *h, const EvolvePlan &ep, const Run &run, void
         a.T = run.geo.T;
         a.nrm2 = nrm2_records ? nrm2_records + 4 * b0 : nullptr;
         a.viol = h->viol_dev;
+        a.swizzle = ep.swizzle;
         int e = hs::launch_tile(a, std::min(lbatch, chunk - b0), c128, true, stream);
         if (e) return hip_fail((hipError_t)e, "tile kernel launch");
     }
@@ -406,11 +435,11 @@ hs_status hs_evolve(hs_factors f, void *psi, int batch, int steps, void *stream,
     if (cur_dev != f->device) return fail(HS_EINVAL, "current device differs from the build device");
     for (int c0 = 0; c0 < batch; c0 += HS_MAX_BATCH) {
         const int chunk = std::min(HS_MAX_BATCH, batch - c0);
-        auto key = std::make_pair(chunk, fuse ? 1 : 0);
+        const PlanKey key = plan_key(chunk, fuse);
         auto it = f->plans.find(key);
         if (it == f->plans.end()) {
             EvolvePlan ep;
-            if (hs_status s = make_evolve_plan(f, chunk, fuse, ep, stream)) return s;
+            if (hs_status s = make_evolve_plan(f, key, ep, stream)) return s;
             it = f->plans.emplace(key, std::move(ep)).first;
         }
         const EvolvePlan &ep = it->second;
@@ -519,11 +548,11 @@ hs_status hs_step_launches(hs_factors f, int batch, unsigned flags, int *n_launc
     std::lock_guard<std::mutex> lock(f->mu);
     const int chunk = std::min(HS_MAX_BATCH, batch);
     const bool fuse = !(flags & HS_NO_FUSE);
-    auto key = std::make_pair(chunk, fuse ? 1 : 0);
+    const PlanKey key = plan_key(chunk, fuse);
     auto it = f->plans.find(key);
     if (it == f->plans.end()) {
         EvolvePlan ep;
-        if (hs_status s = make_evolve_plan(f, chunk, fuse, ep, f->alloc_stream)) return s;
+        if (hs_status s = make_evolve_plan(f, key, ep, f->alloc_stream)) return s;
         it = f->plans.emplace(key, std::move(ep)).first;
         HS_HIP(hipStreamSynchronize(f->alloc_stream), "hipStreamSynchronize");
     }
@@ -610,10 +639,10 @@ hs_status hs_dia_spmv(int n_diags, const long long *offsets, const void *const *
         // when that keeps 256-byte row runs; otherwise use contiguous tiles.
         int q = orall ? __builtin_ctzll(orall) : 0;
         Geo geo = geometry(0, 0, n, Tmax);
-        if (orall && (1 << std::min(q, 20)) >= w_min(dtype) && maxabs >= Tmax) {
+        if (orall && (1 << std::min(q, 20)) >= w_min(dtype, plan_key(chunk, true)) && maxabs >= Tmax) {
             const int need = ilog2(maxabs >> q) + 1;     // levels reaching the farthest offset
             const int logT = std::min(ilog2(Tmax), n);
-            const int kb = std::min(need + 1, logT - ilog2(w_min(dtype)));
+            const int kb = std::min(need + 1, logT - ilog2(w_min(dtype, plan_key(chunk, true))));
             if (kb >= 1) {
                 Geo g2 = geometry(q, q + kb, n, Tmax);
                 if (g2.ok && g2.qb > 0) geo = g2;
@@ -648,6 +677,7 @@ hs_status hs_dia_spmv(int n_diags, const long long *offsets, const void *const *
         a.qb = geo.qb; a.kb = geo.kb; a.logW = geo.logW; a.nlw_log = geo.nlw_log; a.T = geo.T;
         a.nrm2 = nullptr;
         a.viol = nullptr;
+        a.swizzle = 0;
         if (e == hipSuccess) {
             int le = hs::launch_tile(a, chunk, dtype == HS_C128, false, stream);
             e = (hipError_t)le;

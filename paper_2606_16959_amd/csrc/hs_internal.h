@@ -75,6 +75,7 @@ struct TileArgs {
     int32_t qb, kb, logW, nlw_log, T;
     const double *nrm2;      // per-state squared norms to divide out, or null
     int *viol;               // closure-violation flag (closed launches)
+    int32_t swizzle;         // deal contiguous eighths of the tiles to the 8 XCDs
 };
 
 struct ConstructArgs {

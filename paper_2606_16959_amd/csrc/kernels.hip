@@ -145,8 +145,11 @@ typedef const __attribute__((address_space(1))) d2v g_d2;
 #define HS_LOAD(ptr) (*(ptr))
 #endif
 
+// Single entries (odd offsets: the two rows of a pair read halves of the
+// same 16-byte granule, so these loads keep the default cache policy and the
+// second one hits in L2).
 __device__ __forceinline__ C2<float> ld1(const C2<float> *p, int i) {
-    const f2v v = HS_LOAD((g_f2 *)(p) + i);
+    const f2v v = *((g_f2 *)(p) + i);
     return C2<float>{v.x, v.y};
 }
 __device__ __forceinline__ C2<double> ld1(const C2<double> *p, int i) {
@@ -218,11 +221,8 @@ __global__ __launch_bounds__(kTileThreads) void dia_tile_kernel(TileArgs a) {
     const int qb = a.qb, kb = a.kb, logW = a.logW;
     const int W = 1 << logW;
     const int L = 1 << kb;
-#ifndef HS_TILE_XCD_SWIZZLE
-#define HS_TILE_XCD_SWIZZLE 0
-#endif
     int blk = blockIdx.x;
-    if (HS_TILE_XCD_SWIZZLE && (gridDim.x & 7) == 0) {
+    if (a.swizzle && (gridDim.x & 7) == 0) {
         // workgroups are dealt to the 8 XCDs round-robin: give each XCD one
         // contiguous eighth of the tiles
         blk = (blk & 7) * (gridDim.x >> 3) + (blk >> 3);
