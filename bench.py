@@ -39,6 +39,7 @@ WORKLOAD = {
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2606_16959_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dia_tile_tfim2d_n26.json")
+OUT_DIR = os.path.join(ROOT, "profiles")      # where summaries are written (--out-dir)
 
 
 def log(msg):
@@ -168,7 +169,7 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, command):
     stats = rows(trace_dir, "*kernel_stats.csv")
     trace = sorted(rows(trace_dir, "*kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
     tile = [r for r in trace if "dia_tile_kernel" in r["Kernel_Name"]]
-    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    os.makedirs(OUT_DIR, exist_ok=True)
     md = ["# dia_tile_kernel on tfim2d 5x5 + ancilla, n=26, complex64, budget 16", "",
           "Command (repository root, GPU box):", "", "```", command, "```", "",
           "## rocprofv3 --kernel-trace --stats summary", "",
@@ -207,9 +208,9 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, command):
     for j in range(nl):
         md.append(f"| {j} | {sum(durs[j]) / max(1, len(durs[j])):.3f} | {sum(ft[j::nl]) / len(ft[j::nl]):.0f} | "
                   f"{sum(wt[j::nl]) / len(wt[j::nl]):.0f} | {per[j] / 1e9:.3f} |")
-    with open(os.path.join(ROOT, "profiles", "dia_tile_tfim2d_n26.md"), "w") as fh:
+    with open(os.path.join(OUT_DIR, "dia_tile_tfim2d_n26.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(os.path.join(OUT_DIR, os.path.basename(TRAFFIC_FILE)), "w") as fh:
         json.dump({"kernel_sha": kernel_hash(), "bytes_per_launch_scaled": per,
                    "fetch_scale": f_scale, "write_scale": w_scale, "command": command}, fh, indent=1)
     print("\n".join(md))
@@ -293,9 +294,72 @@ def sweep(torch, steps, warmup, rounds=3):
         md.append(f"| {v['name']} | {envs} | {v['launches']} | {v['bytes'] / 1e9:.2f} | {ms:.3f} | "
                   f"{min(v['ms']):.3f}..{max(v['ms']):.3f} | {gbs:.1f} | {100 * gbs / HBM_PEAK_GBS:.1f} | {v['same']} |")
     f.close()
-    with open(os.path.join(ROOT, "profiles", "sweep_launch_plan_tfim2d_n26.md"), "w") as fh:
+    with open(os.path.join(OUT_DIR, "sweep_launch_plan_tfim2d_n26.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
     print("\n".join(md))
+
+
+def other_configs(torch, steps=10, warmup=2):
+    """The other workload configurations in the same harness: per-step time
+    and algorithmic GB/s (n <= 20 states stay in the 256 MB last-level cache,
+    so only n = 24 and n = 26 figures are HBM-bound)."""
+    import paper_2606_16959_amd as hs
+    from workloads import config_hamiltonian, states as ws
+    from workloads.hamiltonians import CONFIG_RUN
+    out = []
+    cases = [(1, "c128", False), (2, "c128", False), (2, "c64", False), (4, "c64", False),
+             (3, "c64", True)]
+    for cfg, dtype, renorm in cases:
+        H = config_hamiltonian(cfg)
+        run = CONFIG_RUN[cfg]
+        npd = np.complex128 if dtype == "c128" else np.complex64
+        elem = 16 if dtype == "c128" else 8
+        f = hs.build_factors(H.strings, H.coeffs, H.n, run["t"], run["steps"], run["budget"], dtype=dtype)
+        B = run["batch"]
+        launches = f.step_launches(B)
+        per = launch_bytes(f.describe(), launches, 1 << H.n, B, elem)
+        psi = torch.from_numpy(np.ascontiguousarray(ws.config_states(cfg, npd))).cuda()
+        for _ in range(warmup):
+            hs.evolve(f, psi, 1, renorm=renorm)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            hs.evolve(f, psi, 1, renorm=renorm)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        row = {"config": cfg, "n": H.n, "batch": B, "dtype": dtype, "renorm": renorm,
+               "launches_per_step": len(launches), "ms_per_step": round(ms, 4),
+               "gb_per_step": round(sum(per) / 1e9, 3), "gbs": round(sum(per) / ms / 1e6, 1)}
+        if B > 1:
+            row["ms_per_state_step"] = round(ms / B, 4)
+        out.append(row)
+        log(f"config {cfg} {dtype} B={B} renorm={renorm}: {ms:.4f} ms/step {row['gbs']} GB/s")
+        f.close()
+        del psi
+        torch.cuda.empty_cache()
+    return out
+
+
+def write_serve_summary(stats, command, fname):
+    md = ["# Served stream: mixed TFIM / Heisenberg / MaxCut / TSP jobs, n in [10, 24], complex64", "",
+          f"Command (repository root, GPU box): `{command}`", "",
+          "Latency = arrival -> completion event of the job's last kernel; queue wait = arrival -> "
+          "admission; service = admission -> completion (factor build + state setup + evolution). "
+          "Oracle check: jobs hashed into a 5% sample with n <= 16, state column 0, FP64 oracle.", "",
+          "| jobs | rate (jobs/s) | completed | p50 ms | p99 ms | max ms | queue p50 ms | service p50 ms | "
+          "service p99 ms | throughput jobs/s | GPU busy | peak active | oracle checked | min fidelity |",
+          "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for st in stats:
+        L, Q, S = st["latency_ms"], st["queue_wait_ms"], st["service_ms"]
+        md.append(f"| {st['jobs']} | {st['rate_jobs_s']:g} | {st['completed']} | {L['p50']:.1f} | {L['p99']:.1f} | "
+                  f"{L['max']:.1f} | {Q['p50']:.1f} | {S['p50']:.1f} | {S['p99']:.1f} | "
+                  f"{st['throughput_jobs_s']:.2f} | {st['gpu_busy_frac']:.3f} | {st['peak_active']} | "
+                  f"{st['oracle_checked']} | {st['oracle_min_fidelity']:.12f} |")
+    with open(os.path.join(OUT_DIR, fname), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md), file=sys.stderr)
 
 
 def main():
@@ -312,11 +376,18 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-oracle-nmax", type=int, default=16)
     ap.add_argument("--serve-only", action="store_true", help="only the served stream")
+    ap.add_argument("--no-other-configs", action="store_true")
+    ap.add_argument("--serve-sweep", default="", help="comma-separated arrival rates (jobs/s)")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
                     help="write profiles/ summaries from rocprofv3 output directories")
     ap.add_argument("--profile-command", default="")
     ap.add_argument("--sweep", action="store_true", help="launch-plan variants (writes profiles/)")
+    ap.add_argument("--out-dir", default=None, help="directory for written summaries (default profiles/)")
     args = ap.parse_args()
+    if args.out_dir:
+        global OUT_DIR
+        OUT_DIR = os.path.abspath(args.out_dir)
+        os.makedirs(OUT_DIR, exist_ok=True)
     if args.summarize_profiles:
         summarize_profiles(*args.summarize_profiles, args.profile_command)
         return
@@ -336,6 +407,17 @@ def main():
     if args.serve_only:
         st = serve_leg(torch, args.serve_jobs, args.serve_rate, args.serve_slots, args.serve_oracle_nmax)
         print(json.dumps({"metric": "served-solve latency", "serve": st}), flush=True)
+        if args.out_dir:
+            write_serve_summary([st], f"python3 bench.py --serve-only --serve-jobs {args.serve_jobs} "
+                                      f"--serve-rate {args.serve_rate} --serve-slots {args.serve_slots}",
+                                f"serve_stream_{args.serve_jobs}jobs_{int(args.serve_rate)}per_s.md")
+        return
+    if args.serve_sweep:
+        rates = [float(r) for r in args.serve_sweep.split(",")]
+        sts = [serve_leg(torch, args.serve_jobs, r, args.serve_slots, args.serve_oracle_nmax) for r in rates]
+        write_serve_summary(sts, f"python3 bench.py --serve-sweep {args.serve_sweep} --serve-jobs "
+                                 f"{args.serve_jobs} --serve-slots {args.serve_slots}",
+                            f"serve_rate_sweep_{args.serve_jobs}jobs.md")
         return
     H = config_hamiltonian(3)
     N = 1 << H.n
@@ -402,6 +484,11 @@ def main():
         cpu = cpu_baseline(H, psi0, budget, t, steps_total, args.cpu_steps, step_bytes)
         log(f"oracle {cpu['ms_per_step']} ms/step ({cpu['cores']} threads)")
 
+    others = None
+    if not args.no_other_configs:
+        f.close()
+        torch.cuda.empty_cache()
+        others = other_configs(torch)
     serve = None
     if args.serve_jobs > 0:
         f.close()
@@ -419,7 +506,7 @@ def main():
         "step_ms_median": round(float(np.median(step_ms)), 4),
         "step_ms_p90": round(float(np.percentile(step_ms, 90)), 4),
         "bytes_per_step": int(step_bytes), "build_s": round(build_s, 3),
-        "closure_ok": bool(closure_ok), **extra, "serve": serve,
+        "closure_ok": bool(closure_ok), **extra, "other_configs": others, "serve": serve,
     }
     print(json.dumps(line), flush=True)
     f.close()
