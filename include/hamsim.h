@@ -159,7 +159,7 @@ hs_status hs_free_factors(hs_factors f);
 /*
  * hs_dia_spmv -- y = A x for an arbitrary operator in the diagonal layout
  * (Alg. 1), out of place, for `batch` vectors ([batch][N]).
- *   n_diags     number of stored diagonals (1..64)
+ *   n_diags     number of stored diagonals (1..65535)
  *   offsets     host array, strictly ascending, each in (-N, N)
  *   diags       host array of n_diags device pointers; diags[j] holds
  *               N - |offsets[j]| entries of `dtype`
@@ -183,6 +183,63 @@ hs_status hs_norm2(const void *psi, int batch, long long N, hs_dtype dtype, void
  */
 hs_status hs_fidelity(const void *phi, int phi_dtype, const void *psi, int psi_dtype,
                       int batch, long long N, void *stream, double *out);
+
+/* ------------------------------------------------------------------------
+ * General operators in the diagonal layout, device resident.  These carry
+ * the paper's single-propagator pipeline: H is stored by its diagonals, its
+ * short-time propagator U ~ exp(-i H dt) is built by a truncated Taylor
+ * series of SpGEMM products (Alg. 2), the step count can be chosen as the
+ * smallest one whose propagator meets the diagonal budget (Section 3.1
+ * flowchart, Eq. 5), and U is applied repeatedly to the state (Alg. 3).
+ * Entries are complex128 (FP64) unless converted with hs_dia_to_c64.
+ * Memory is allocated and released stream-ordered on the stream given at
+ * creation, which must stay valid until hs_dia_free.
+ * ------------------------------------------------------------------------ */
+typedef struct hs_dia_s *hs_dia;
+
+/* H = sum_k c_k P_k by its diagonals; diagonals whose entries all cancel
+ * (e.g. XX + YY on the offsets +-3 of a bond) are not stored.  Same string
+ * and coefficient conventions as hs_plan.  Synchronises `stream`. */
+hs_status hs_dia_from_pauli(int n_qubits, int n_terms, const char *const *pauli_terms,
+                            const double *coeffs, void *stream, hs_dia *out);
+/* An operator from host diagonals: host_diags[j] holds N - |offsets[j]|
+ * complex128 entries (interleaved re, im), storage index min(row, col);
+ * offsets strictly ascending.  Synchronises `stream`. */
+hs_status hs_dia_from_host(long long N, int n_diags, const long long *offsets,
+                           const double *const *host_diags, void *stream, hs_dia *out);
+hs_status hs_dia_info(hs_dia A, long long *N, int *n_diags, int *dtype);
+hs_status hs_dia_offsets(hs_dia A, long long *offsets, int cap);
+/* entries [start, start + count) of diagonal j to host memory; syncs */
+hs_status hs_dia_copy_diagonal(hs_dia A, int j, long long start, long long count, void *host_dst,
+                               void *stream);
+/* C = A B (complex128).  C's diagonals are every a + b in (-N, N) of A's and
+ * B's offsets (structural: no cancellation check); entry (r, r+c) sums
+ * A[r, r+a] B[r+a, r+c] over the pairs a + b = c, in ascending a (the
+ * paper's SpGEMM, Section 3.3).  Synchronises `stream`. */
+hs_status hs_dia_spgemm(hs_dia A, hs_dia B, void *stream, hs_dia *C);
+/* largest entry modulus (FP64); syncs */
+hs_status hs_dia_maxabs(hs_dia A, void *stream, double *out);
+/* Alg. 2: X = -i H dt; U = T = I; for k = 1..max_iter: T <- T X / k; stop
+ * when max |T_ij| < tol (T not added), else U += T.  A diagonal H takes the
+ * exact elementwise exponential.  *n_terms = the number of Taylor terms added
+ * after I (0 for diagonal H).  No scaling-and-squaring.  Syncs. */
+hs_status hs_spme(hs_dia H, double dt, double tol, int max_iter, void *stream, hs_dia *U,
+                  int *n_terms);
+/* Smallest r such that hs_spme(H, t / r, tol, max_iter) has at most `budget`
+ * diagonals (structural count): r = 1 for diagonal H; else r = 1 if it
+ * meets the budget, otherwise doubling u = 2, 4, ... until it does, then
+ * bisection between the last failing and the first passing value.  A probe
+ * stops as soon as a Taylor term above the tolerance would push the count
+ * past the budget, without storing that term.  HS_EBUDGET above 2^24.  Syncs. */
+hs_status hs_estimate_timesteps(hs_dia H, double t, int budget, double tol, int max_iter,
+                                void *stream, int *steps);
+/* complex64 copy of a complex128 operator (round to nearest); syncs */
+hs_status hs_dia_to_c64(hs_dia A, void *stream, hs_dia *out);
+/* Alg. 3's loop: psi <- U^steps psi for `batch` device states of U's dtype,
+ * by repeated DIA SpMV (out of place with library scratch, result written
+ * back to psi).  Synchronises `stream`. */
+hs_status hs_dia_evolve(hs_dia U, void *psi, int batch, int steps, void *stream);
+hs_status hs_dia_free(hs_dia A);
 
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *hs_last_error(void);

@@ -1,0 +1,139 @@
+"""Sparse matrix exponential by truncated Taylor series, the diagonal-budget
+step search and the single-propagator simulation loop, in FP64 (test
+infrastructure only).
+
+Paper: Alg. 2 (SpME: X = -i A t; U = T = I; T <- T X / i; stop when the norm
+of T falls below the tolerance, 1e-6 as printed; otherwise U += T), Alg. 3
+(n = EstimateTimesteps(A, T, D_max); dt = T / n; U = SpME(A, dt); n times
+x <- U x), the EstimateTimesteps flowchart of Section 3.1 and Eq. 5
+(smallest r with num_diags(e^{-i H t / r}) <= D_max), the structural dry run
+of Section 3.2 (the output diagonal set is known from the offsets alone).
+
+Readings where the paper is silent:
+
+* ``T.norm()`` is the largest entry modulus of T.
+* num_diags of the propagator is its structural diagonal count: the union of
+  the offset sets of the kept Taylor terms, where term k's offsets are the
+  k-fold sums of H's (numerically nonzero) offsets, clipped to (-N, N).
+* A diagonal H takes the exact elementwise exponential (Section 3.3), K = 0.
+* Scaling-and-squaring is not applied (each squaring doubles the offset set,
+  which works against the budget).
+* EstimateTimesteps: a diagonal H needs r = 1; otherwise l = 1; if the
+  budget holds at l, r = l; else u = 2 l, l <- u while the budget fails at u
+  (doubling), then binary search on (l_prev, u] for the smallest feasible r.
+* max_iterations defaults to 30.
+
+The Taylor sum is formed with a library sparse matrix product
+(scipy.sparse, CSR) in the order T_k = T_{k-1} X / k.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from .pauli import parse_terms, popcount_array
+
+DEFAULT_TOL = 1e-6
+DEFAULT_MAX_ITER = 30
+
+
+def hamiltonian_csr(terms, n: int) -> sp.csr_matrix:
+    """H as a sparse matrix from the Pauli action H[y, y^m] += c i^ny (-1)^{popcount((y^m)&z)}."""
+    N = 1 << n
+    rows, cols, vals = [], [], []
+    y = np.arange(N, dtype=np.int64)
+    for t in terms:
+        col = y ^ t.xmask
+        sign = 1.0 - 2.0 * (popcount_array(col & t.zmask) & 1)
+        rows.append(y)
+        cols.append(col)
+        vals.append(t.coeff * (1j) ** t.ny * sign)
+    H = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(N, N), dtype=np.complex128)
+    H.sum_duplicates()
+    H.eliminate_zeros()
+    return H
+
+
+def offsets_of(M) -> list:
+    """Offsets (col - row) of the diagonals holding a nonzero entry."""
+    C = sp.coo_matrix(M)
+    nz = C.data != 0
+    return sorted(set((C.col[nz] - C.row[nz]).tolist()))
+
+
+def sumset(a, b, N) -> list:
+    return sorted({x + y for x in a for y in b if -N < x + y < N})
+
+
+def spme(H: sp.csr_matrix, dt: float, tol: float = DEFAULT_TOL, max_iter: int = DEFAULT_MAX_ITER):
+    """Truncated Taylor series of exp(-i H dt).
+
+    Returns (U, K, offsets): U as CSR, K = number of terms added after the
+    identity, and the structural offset set of U."""
+    N = H.shape[0]
+    offX = offsets_of(H)
+    if offX in ([], [0]):
+        # diagonal H: the exponential is exact and elementwise (Section 3.3)
+        d = H.diagonal()
+        return sp.diags(np.cos(-dt * d.real) + 1j * np.sin(-dt * d.real), format="csr"), 0, [0]
+    X = (H * (-1j * dt)).tocsr()
+    U = sp.identity(N, dtype=np.complex128, format="csr")
+    T = sp.identity(N, dtype=np.complex128, format="csr")
+    offT = [0]
+    offU = {0}
+    K = 0
+    for i in range(1, max_iter + 1):
+        T = (T @ X) / i
+        offT = sumset(offT, offX, N)
+        norm = float(np.max(np.abs(T.data))) if T.nnz else 0.0
+        if norm < tol:
+            break
+        U = U + T
+        offU.update(offT)
+        K = i
+    return U.tocsr(), K, sorted(offU)
+
+
+def num_diags(H, t, r, tol=DEFAULT_TOL, max_iter=DEFAULT_MAX_ITER) -> int:
+    return len(spme(H, t / r, tol, max_iter)[2])
+
+
+def estimate_timesteps(H, t, budget, tol=DEFAULT_TOL, max_iter=DEFAULT_MAX_ITER, r_max=1 << 24):
+    """Smallest r with num_diags(SpME(H, t/r)) <= budget (flowchart of Section 3.1)."""
+    if offsets_of(H) in ([], [0]):
+        return 1
+
+    def ok(r):
+        return num_diags(H, t, r, tol, max_iter) <= budget
+
+    lo = 1
+    if ok(lo):
+        return lo
+    u = 2 * lo
+    while not ok(u):
+        lo = u
+        u *= 2
+        if u > r_max:
+            raise ValueError("no feasible step count below r_max")
+    # smallest feasible in (lo, u]
+    while u - lo > 1:
+        mid = (lo + u) // 2
+        if ok(mid):
+            u = mid
+        else:
+            lo = mid
+    return u
+
+
+def simulate(H, psi0: np.ndarray, t: float, r: int, tol=DEFAULT_TOL, max_iter=DEFAULT_MAX_ITER):
+    """Alg. 3 with a given r: U = SpME(H, t/r); r times psi <- U psi."""
+    U, K, offs = spme(H, t / r, tol, max_iter)
+    psi = np.array(psi0, dtype=np.complex128, copy=True)
+    for _ in range(r):
+        psi = (U @ psi.T).T if psi.ndim == 2 else U @ psi
+    return psi, K, offs
+
+
+def hamiltonian_from_strings(strings, coeffs, n):
+    return hamiltonian_csr(parse_terms(strings, coeffs, n), n)

@@ -41,6 +41,18 @@ _SIG = {
     "hs_dia_spmv": (_I, [_I, _P, _P, _P, _P, _I, _LL, _I, _P]),
     "hs_norm2": (_I, [_P, _I, _LL, _I, _P, _P]),
     "hs_fidelity": (_I, [_P, _I, _P, _I, _I, _LL, _P, _P]),
+    "hs_dia_from_pauli": (_I, [_I, _I, _P, _P, _P, ctypes.POINTER(_P)]),
+    "hs_dia_from_host": (_I, [_LL, _I, _P, _P, _P, ctypes.POINTER(_P)]),
+    "hs_dia_info": (_I, [_P, ctypes.POINTER(_LL), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "hs_dia_offsets": (_I, [_P, _P, _I]),
+    "hs_dia_copy_diagonal": (_I, [_P, _I, _LL, _LL, _P, _P]),
+    "hs_dia_spgemm": (_I, [_P, _P, _P, ctypes.POINTER(_P)]),
+    "hs_dia_maxabs": (_I, [_P, _P, ctypes.POINTER(_D)]),
+    "hs_spme": (_I, [_P, _D, _D, _I, _P, ctypes.POINTER(_P), ctypes.POINTER(_I)]),
+    "hs_estimate_timesteps": (_I, [_P, _D, _I, _D, _I, _P, ctypes.POINTER(_I)]),
+    "hs_dia_to_c64": (_I, [_P, _P, ctypes.POINTER(_P)]),
+    "hs_dia_evolve": (_I, [_P, _P, _I, _I, _P]),
+    "hs_dia_free": (_I, [_P]),
     "hs_last_error": (ctypes.c_char_p, []),
     "hs_abi_version": (_I, []),
 }

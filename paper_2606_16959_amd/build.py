@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhamsim.so")
-SOURCES = ["plan.cpp", "api.hip", "kernels.hip"]
+SOURCES = ["plan.cpp", "api.hip", "kernels.hip", "dia_api.hip", "dia_ops.hip"]
 ARCH = os.environ.get("HAMSIM_OFFLOAD_ARCH", "gfx950")
 
 

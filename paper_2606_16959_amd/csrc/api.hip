@@ -17,11 +17,13 @@
 #include <vector>
 
 #include "hs_internal.h"
+#include "tile_plan.h"
 
 using hs::DiagDesc;
 using hs::Factor;
 using hs::Plan;
 using hs::TileArgs;
+using namespace hs::plan;
 
 namespace {
 
@@ -31,6 +33,14 @@ hs_status fail(hs_status s, const std::string &m) {
     g_err = m;
     return s;
 }
+
+}  // namespace
+
+namespace hs {
+void set_last_error(const std::string &m) { g_err = m; }
+}  // namespace hs
+
+namespace {
 
 hs_status hip_fail(hipError_t e, const char *what) {
     g_err = std::string(what) + ": " + hipGetErrorString(e);
@@ -42,70 +52,6 @@ hs_status hip_fail(hipError_t e, const char *what) {
         hipError_t e_ = (call);                             \
         if (e_ != hipSuccess) return hip_fail(e_, what);    \
     } while (0)
-
-int ilog2(int64_t v) {
-    int l = 0;
-    while ((int64_t(1) << (l + 1)) <= v) ++l;
-    return l;
-}
-
-size_t elem_bytes(int dtype) { return dtype == HS_C128 ? 16 : 8; }
-
-// Tile geometry for coupling hull [lb, hb) of bits.
-struct Geo {
-    int qb = 0, kb = 0, logW = 0, nlw_log = 0, T = 0;
-    bool ok = false;
-};
-
-// Largest tile (rows) one launch of `batch` states holds.
-int tile_rows_max(int dtype, int batch) { return hs::tile_rows_cap(dtype == HS_C128, batch); }
-
-// Launch-plan tuning knobs, read from the environment at every evolve (a
-// handle keeps one plan per batch size and knob setting): HAMSIM_WMIN_BYTES (shortest run of consecutive rows a
-// strided tile may have, default 256), HAMSIM_MAX_FUSE (factors per launch,
-// default 8), HAMSIM_XCD_SWIZZLE (0/1, default 1: each XCD gets one
-// contiguous eighth of the tiles instead of every eighth tile).
-int env_int(const char *name, int dflt, int lo, int hi) {
-    const char *v = std::getenv(name);
-    if (!v || !*v) return dflt;
-    char *end = nullptr;
-    long x = std::strtol(v, &end, 10);
-    if (end == v) return dflt;
-    return (int)std::min<long>(hi, std::max<long>(lo, x));
-}
-struct PlanKey {
-    int chunk, fuse, wmin_bytes, max_fuse, swizzle;
-    bool operator<(const PlanKey &o) const {
-        return std::tie(chunk, fuse, wmin_bytes, max_fuse, swizzle) <
-               std::tie(o.chunk, o.fuse, o.wmin_bytes, o.max_fuse, o.swizzle);
-    }
-};
-PlanKey plan_key(int chunk, bool fuse) {
-    return PlanKey{chunk, fuse ? 1 : 0, env_int("HAMSIM_WMIN_BYTES", 256, 8, 1 << 20),
-                   env_int("HAMSIM_MAX_FUSE", hs::kMaxRun, 1, hs::kMaxRun),
-                   env_int("HAMSIM_XCD_SWIZZLE", 1, 0, 1)};
-}
-int w_min(int dtype, const PlanKey &k) { return std::max(1, k.wmin_bytes / (dtype == HS_C128 ? 16 : 8)); }
-
-Geo geometry(int lb, int hb, int n, int Tmax) {
-    Geo g;
-    hb = std::min(hb, n);
-    lb = std::min(lb, hb);
-    const int logT = std::min(ilog2(Tmax), n);
-    if (hb <= logT) {               // contiguous tile of 2^logT rows
-        g.qb = 0; g.kb = logT; g.logW = 0; g.nlw_log = 0; g.T = 1 << logT; g.ok = true;
-        return g;
-    }
-    const int kb = hb - lb;
-    if (kb > logT) return g;
-    g.qb = lb;
-    g.kb = kb;
-    g.logW = std::min(logT - kb, lb);
-    g.nlw_log = lb - g.logW;
-    g.T = 1 << (kb + g.logW);
-    g.ok = true;
-    return g;
-}
 
 struct Run {
     std::vector<int> factors;   // consecutive factor indices
@@ -323,6 +269,8 @@ static hs_status build_device(hs_factors_s *h, void *stream) {
 
     // temporaries: phase table and per-factor tables
     std::vector<void *> temps;
+    std::vector<std::vector<uint64_t>> host_keep;   // sources of async uploads, alive until the sync
+    std::vector<std::vector<double>> host_keep_d;
     auto cleanup = [&]() {
         for (void *p : temps) (void)hipFreeAsync(p, st);
     };
@@ -336,8 +284,10 @@ static hs_status build_device(hs_factors_s *h, void *stream) {
     double *phase = nullptr;
     hipError_t e = hipSuccess;
     if (!P.diag.empty()) {
-        std::vector<uint64_t> zm;
-        std::vector<double> cf;
+        host_keep.emplace_back();
+        host_keep_d.emplace_back();
+        std::vector<uint64_t> &zm = host_keep.back();
+        std::vector<double> &cf = host_keep_d.back();
         for (int k : P.diag) {
             zm.push_back(P.terms[k].z);
             cf.push_back(P.terms[k].c);
@@ -359,7 +309,8 @@ static hs_status build_device(hs_factors_s *h, void *stream) {
         a.base = f.dev;
         a.N = (int32_t)P.N;
         a.smask = (uint32_t)f.smask;
-        std::vector<uint64_t> eo(f.elem_off.begin(), f.elem_off.end());
+        host_keep.emplace_back(f.elem_off.begin(), f.elem_off.end());
+        const std::vector<uint64_t> &eo = host_keep.back();
         void *doffs = nullptr, *deo = nullptr, *dL = nullptr;
         if ((e = upload(f.offs.data(), f.offs.size() * 8, &doffs)) != hipSuccess ||
             (e = upload(eo.data(), eo.size() * 8, &deo)) != hipSuccess) {
@@ -607,7 +558,7 @@ hs_status hs_free_factors(hs_factors f) {
 hs_status hs_dia_spmv(int n_diags, const long long *offsets, const void *const *diags, const void *x,
                       void *y, int batch, long long N, hs_dtype dtype, void *stream) {
     if (dtype != HS_C64 && dtype != HS_C128) return fail(HS_EINVAL, "bad dtype");
-    if (n_diags < 1 || n_diags > 64 || !offsets || !diags || !x || !y || batch < 1)
+    if (n_diags < 1 || n_diags > 65535 || !offsets || !diags || !x || !y || batch < 1)
         return fail(HS_EINVAL, "bad arguments");
     if (N < 1 || N > (1ll << HS_MAX_QUBITS) || (N & (N - 1)))
         return fail(HS_EINVAL, "N must be a power of two <= 2^30");
@@ -618,70 +569,24 @@ hs_status hs_dia_spmv(int n_diags, const long long *offsets, const void *const *
     if (xb < yb + span && yb < xb + span) return fail(HS_EINVAL, "x and y overlap");
     if (reinterpret_cast<uintptr_t>(x) % 16 || reinterpret_cast<uintptr_t>(y) % 16)
         return fail(HS_EINVAL, "x and y must be 16-byte aligned");
-    uint64_t orall = 0;
-    long long maxabs = 0;
     for (int j = 0; j < n_diags; ++j) {
         if (offsets[j] <= -N || offsets[j] >= N) return fail(HS_EINVAL, "offset out of range");
         if (j && offsets[j] <= offsets[j - 1]) return fail(HS_EINVAL, "offsets must ascend strictly");
         if (!diags[j]) return fail(HS_EINVAL, "null diagonal pointer");
         if (reinterpret_cast<uintptr_t>(diags[j]) % 16) return fail(HS_EINVAL, "diagonals must be 16-byte aligned");
-        const long long a = offsets[j] < 0 ? -offsets[j] : offsets[j];
-        orall |= (uint64_t)a;
-        maxabs = std::max(maxabs, a);
     }
-    const int n = ilog2(N);
-    const int chunk_max = HS_MAX_BATCH;
-    std::vector<DiagDesc> hd(n_diags);
-    for (int c0 = 0; c0 < batch; c0 += chunk_max) {
-        const int chunk = std::min(chunk_max, batch - c0);
-        const int Tmax = tile_rows_max(dtype, chunk);
-        // Stride the tile by the largest power of two dividing every offset
-        // when that keeps 256-byte row runs; otherwise use contiguous tiles.
-        int q = orall ? __builtin_ctzll(orall) : 0;
-        Geo geo = geometry(0, 0, n, Tmax);
-        if (orall && (1 << std::min(q, 20)) >= w_min(dtype, plan_key(chunk, true)) && maxabs >= Tmax) {
-            const int need = ilog2(maxabs >> q) + 1;     // levels reaching the farthest offset
-            const int logT = std::min(ilog2(Tmax), n);
-            const int kb = std::min(need + 1, logT - ilog2(w_min(dtype, plan_key(chunk, true))));
-            if (kb >= 1) {
-                Geo g2 = geometry(q, q + kb, n, Tmax);
-                if (g2.ok && g2.qb > 0) geo = g2;
-            }
-        }
-        for (int j = 0; j < n_diags; ++j) {
-            const long long d = offsets[j];
-            DiagDesc &dd = hd[j];
-            dd = DiagDesc{};
-            dd.ptr = diags[j];
-            dd.off = (int32_t)d;
-            const long long lowmask = (1ll << geo.qb) - 1;
-            dd.regular = (d & lowmask) == 0;
-            dd.m = dd.regular ? (int32_t)(d >> geo.qb) : 0;
-            dd.lo = (int32_t)std::max<long long>(0, -d);
-            dd.hi = (int32_t)std::min<long long>(N, N - d);
-        }
+    std::vector<DiagDesc> hd;
+    for (int c0 = 0; c0 < batch; c0 += HS_MAX_BATCH) {
+        const int chunk = std::min(HS_MAX_BATCH, batch - c0);
+        const Geo geo = generic_geometry(offsets, n_diags, N, dtype, chunk);
+        fill_descs(offsets, diags, n_diags, N, geo, hd);
         DiagDesc *ddev = nullptr;
         hipStream_t st = reinterpret_cast<hipStream_t>(stream);
         HS_HIP(hipMallocAsync(reinterpret_cast<void **>(&ddev), sizeof(DiagDesc) * n_diags, st),
                "hipMallocAsync(descriptors)");
         hipError_t e = hipMemcpyAsync(ddev, hd.data(), sizeof(DiagDesc) * n_diags, hipMemcpyHostToDevice, st);
-        TileArgs a{};
-        a.y = yb + (size_t)c0 * N * sc;
-        a.x = xb + (size_t)c0 * N * sc;
-        a.stride = N;
-        a.N = (int32_t)N;
-        a.nf = 1;
-        a.dstart[0] = 0;
-        a.dstart[1] = n_diags;
-        a.desc = ddev;
-        a.qb = geo.qb; a.kb = geo.kb; a.logW = geo.logW; a.nlw_log = geo.nlw_log; a.T = geo.T;
-        a.nrm2 = nullptr;
-        a.viol = nullptr;
-        a.swizzle = 0;
-        if (e == hipSuccess) {
-            int le = hs::launch_tile(a, chunk, dtype == HS_C128, false, stream);
-            e = (hipError_t)le;
-        }
+        const TileArgs a = open_args(geo, ddev, n_diags, xb + (size_t)c0 * N * sc, yb + (size_t)c0 * N * sc, N);
+        if (e == hipSuccess) e = (hipError_t)hs::launch_tile(a, chunk, dtype == HS_C128, false, stream);
         hipError_t e2 = hipStreamSynchronize(st);
         (void)hipFreeAsync(ddev, st);
         if (e != hipSuccess) return hip_fail(e, "dia_spmv launch");

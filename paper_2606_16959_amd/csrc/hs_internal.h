@@ -104,6 +104,52 @@ int launch_reduce(const void *A, int ta, const void *B, int tb, int batch, int64
                   double *partial, int G, double *out, bool dot, void *stream);
 int launch_scale(void *psi, int64_t N, int batch, const double *nrm2, bool c128, void *stream);
 
+// general operators in the diagonal layout (dia_ops.hip)
+struct PauliDiaArgs {
+    int64_t N;
+    const int64_t *offs;          // [nd] candidate offsets
+    double *const *out;           // [nd] output diagonals (FP64 complex)
+    int n_cls;                    // distinct X-masks
+    const uint64_t *cls_mask;     // [n_cls]
+    const int *cls_ptr;           // [n_cls + 1] into the term arrays
+    const uint64_t *zmask;        // terms sorted by X-mask
+    const double *coeff;
+    const int *ny;
+};
+struct SpgemmArgs {
+    int64_t N;
+    const int64_t *a_offs;
+    const double *const *a_ptr;
+    const double *const *b_ptr;
+    const int64_t *c_offs;
+    double *const *c_ptr;
+    const int *cptr;              // [nc + 1] contributor ranges
+    const int *pairs;             // [2 * n_pairs] (index into A, index into B)
+    double scale_re, scale_im;
+    double *block_max;            // [nc][gridDim.x] largest entry modulus per block
+};
+struct DiaAddArgs {
+    int64_t N;
+    const int64_t *offs;
+    const int *ia, *ib;           // source diagonal per output diagonal, -1 = none
+    const double *const *a_ptr;
+    const double *const *b_ptr;
+    double *const *out;
+};
+int dia_grid_x(int64_t len);
+int launch_pauli_dia(const PauliDiaArgs &a, int nd, void *stream);
+int launch_spgemm(const SpgemmArgs &a, int nd, int gx, bool store, void *stream);
+int launch_dia_add(const DiaAddArgs &a, int nd, void *stream);
+int launch_dia_maxabs(const double *const *ptrs, const int64_t *offs, int64_t N, int nd, int gx,
+                      double *block_max, void *stream);
+int launch_dia_fill(double *out, int64_t len, double re, double im, void *stream);
+int launch_diag_exp(const double *h, double *out, int64_t len, double dt, void *stream);
+void set_last_error(const std::string &m);   // message returned by hs_last_error()
+hs_status parse_terms(int n, int n_terms, const char *const *strings, const double *coeffs,
+                      std::vector<Term> &terms, std::string &msg);
+int launch_dia_to_c64(const double *const *src, float *const *dst, const int64_t *offs, int64_t N,
+                      int nd, void *stream);
+
 constexpr int kReduceBlocks = 1024;   // partial sums per state (fixed: determinism)
 
 // Tile-kernel shape (compile-time; the launch planner and the kernels must agree).

@@ -102,41 +102,10 @@ int count_diags(const std::vector<Term> &terms, const std::vector<int> &members,
 
 }  // namespace
 
-void layout_factor(Factor &f, int64_t N, size_t elem_bytes) {
-    const size_t align = kDiagAlignBytes / elem_bytes;
-    size_t pos = 0;
-    f.elem_off.clear();
-    for (int64_t d : f.offs) {
-        f.elem_off.push_back(pos);
-        const size_t len = (size_t)(N - (d < 0 ? -d : d));
-        pos += (len + align - 1) / align * align;
-    }
-    f.elems_total = pos;
-}
-
-hs_status make_plan(int n, int n_terms, const char *const *strings, const double *coeffs,
-                    double t, int steps, int budget, unsigned flags, Plan &P, std::string &msg) {
+hs_status parse_terms(int n, int n_terms, const char *const *strings, const double *coeffs,
+                      std::vector<Term> &terms, std::string &msg) {
     char buf[256];
-    if (n < 1 || n > HS_MAX_QUBITS) {
-        snprintf(buf, sizeof buf, "n_qubits=%d outside [1, %d]", n, HS_MAX_QUBITS);
-        msg = buf;
-        return n > HS_MAX_QUBITS ? HS_ETOOLARGE : HS_EINVAL;
-    }
-    if (n_terms < 1 || !strings || !coeffs) { msg = "need n_terms >= 1, strings and coeffs"; return HS_EINVAL; }
-    if (steps < 1) { msg = "steps must be >= 1"; return HS_EINVAL; }
-    if (budget < 1) { msg = "budget must be >= 1"; return HS_EINVAL; }
-    if (!std::isfinite(t)) { msg = "t must be finite"; return HS_EINVAL; }
-    if (flags & ~(unsigned)HS_MERGE_DIAG) { msg = "unknown build flag"; return HS_EINVAL; }
-
-    P = Plan();
-    P.n = n;
-    P.N = (int64_t)1 << n;
-    P.t = t;
-    P.steps = steps;
-    P.dt = t / steps;
-    P.budget = budget;
-    P.flags = flags;
-
+    terms.clear();
     double cmax = 0.0;
     for (int k = 0; k < n_terms; ++k) {
         const double re = coeffs[2 * k], im = coeffs[2 * k + 1];
@@ -174,8 +143,48 @@ hs_status make_plan(int n, int n_terms, const char *const *strings, const double
             return HS_EINVAL;
         }
         tm.c = coeffs[2 * k];
-        P.terms.push_back(tm);
+        terms.push_back(tm);
     }
+
+    return HS_OK;
+}
+
+void layout_factor(Factor &f, int64_t N, size_t elem_bytes) {
+    const size_t align = kDiagAlignBytes / elem_bytes;
+    size_t pos = 0;
+    f.elem_off.clear();
+    for (int64_t d : f.offs) {
+        f.elem_off.push_back(pos);
+        const size_t len = (size_t)(N - (d < 0 ? -d : d));
+        pos += (len + align - 1) / align * align;
+    }
+    f.elems_total = pos;
+}
+
+hs_status make_plan(int n, int n_terms, const char *const *strings, const double *coeffs,
+                    double t, int steps, int budget, unsigned flags, Plan &P, std::string &msg) {
+    char buf[256];
+    if (n < 1 || n > HS_MAX_QUBITS) {
+        snprintf(buf, sizeof buf, "n_qubits=%d outside [1, %d]", n, HS_MAX_QUBITS);
+        msg = buf;
+        return n > HS_MAX_QUBITS ? HS_ETOOLARGE : HS_EINVAL;
+    }
+    if (n_terms < 1 || !strings || !coeffs) { msg = "need n_terms >= 1, strings and coeffs"; return HS_EINVAL; }
+    if (steps < 1) { msg = "steps must be >= 1"; return HS_EINVAL; }
+    if (budget < 1) { msg = "budget must be >= 1"; return HS_EINVAL; }
+    if (!std::isfinite(t)) { msg = "t must be finite"; return HS_EINVAL; }
+    if (flags & ~(unsigned)HS_MERGE_DIAG) { msg = "unknown build flag"; return HS_EINVAL; }
+
+    P = Plan();
+    P.n = n;
+    P.N = (int64_t)1 << n;
+    P.t = t;
+    P.steps = steps;
+    P.dt = t / steps;
+    P.budget = budget;
+    P.flags = flags;
+
+    if (hs_status st = parse_terms(n, n_terms, strings, coeffs, P.terms, msg)) return st;
 
     // first-fit grouping
     std::vector<std::vector<int>> groups;
