@@ -54,8 +54,10 @@ def kernel_hash() -> str:
 def launch_bytes(desc, launches, N, batch, elem):
     """Algorithmic bytes of each launch of one step."""
     out = []
+    seq = desc.get("sequence") or list(range(len(desc["factors"])))
     for first, cnt in launches:
-        coef = sum((N - abs(d)) * elem for f in desc["factors"][first:first + cnt] for d in f["offsets"])
+        facs = [desc["factors"][k] for k in seq[first:first + cnt]]
+        coef = sum((N - abs(d)) * elem for f in facs for d in f["offsets"])
         out.append(coef + 2 * batch * N * elem)
     return out
 
@@ -362,6 +364,49 @@ def write_serve_summary(stats, command, fname):
     print("\n".join(md), file=sys.stderr)
 
 
+def single_propagator_leg(torch, n=24, budget=None, timed_steps=20):
+    """The paper's own pipeline on a 1-D TFIM (h = 1, t = 1): step search
+    under the diagonal budget (Section 3.1), truncated-Taylor SpME from
+    SpGEMM (Alg. 2), then the Alg. 3 loop x <- U x (complex64), timed over
+    `timed_steps` SpMVs.  Algorithmic bytes per SpMV: every stored diagonal of
+    U once plus the state read and written."""
+    import paper_2606_16959_amd.dia as hd
+    from workloads import hamiltonians as wh, states as ws
+    Hw = wh.tfim_1d(n, 1.0, 1.0)
+    budget = budget or 2 * n + 1
+    N = 1 << n
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = hd.from_pauli(Hw.strings, Hw.coeffs, n)
+    t1 = time.perf_counter()
+    r = hd.estimate_timesteps(H, 1.0, budget)
+    t2 = time.perf_counter()
+    U, K = hd.spme(H, 1.0 / r)
+    t3 = time.perf_counter()
+    U64 = U.to_c64()
+    offs = U64.offsets
+    U.close()
+    H.close()
+    psi = torch.from_numpy(ws.random_phase_state(n, 7, np.complex64)).cuda()
+    hd.evolve(U64, psi, 2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    hd.evolve(U64, psi, timed_steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / timed_steps
+    nbytes = sum((N - abs(d)) * 8 for d in offs) + 2 * N * 8
+    U64.close()
+    out = {"workload": f"tfim1d_n{n}_h1_t1", "budget": budget, "steps_chosen": r, "taylor_terms": K,
+           "propagator_diagonals": len(offs), "build_h_s": round(t1 - t0, 3),
+           "step_search_s": round(t2 - t1, 3), "spme_s": round(t3 - t2, 3),
+           "spmv_ms": round(ms, 4), "spmv_gbs": round(nbytes / ms / 1e6, 1),
+           "full_run_s_estimate": round(ms * r / 1e3, 3)}
+    log(f"single propagator: r={r} K={K} diags={len(offs)} spmv {ms:.3f} ms {out['spmv_gbs']} GB/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -489,6 +534,7 @@ def main():
         f.close()
         torch.cuda.empty_cache()
         others = other_configs(torch)
+        others.append({"single_propagator": single_propagator_leg(torch)})
     serve = None
     if args.serve_jobs > 0:
         f.close()

@@ -56,6 +56,10 @@ typedef enum {
 
 /* build flags */
 #define HS_MERGE_DIAG 1u    /* fold the diagonal factor D into the first group (U_1 D); default in Python */
+#define HS_ORDER2 8u        /* symmetric second-order product (future-work section): per step
+                               F_1..F_{L-1}(dt/2) F_L(dt) F_{L-1}..F_1(dt/2), F = (D, G_1..G_m) */
+#define HS_ORDER4 16u       /* fourth-order Suzuki product: S2(p dt)^2 S2((1-4p) dt) S2(p dt)^2,
+                               p = 1/(4 - 4^(1/3)).  Orders 2 and 4 keep D a factor of its own. */
 /* evolve flags */
 #define HS_RENORM 2u        /* divide each state by its FP64 norm after every step */
 #define HS_NO_FUSE 4u       /* one launch per factor instead of fused multi-factor tiles */
@@ -85,7 +89,7 @@ typedef enum {
  *   coeffs       2*n_terms doubles, (re, im) per term; H must be Hermitian
  *   t            total time; steps >= 1 Trotter steps; dt = t / steps
  *   budget       >= 1, maximum diagonals per factor
- *   flags        HS_MERGE_DIAG or 0
+ *   flags        HS_MERGE_DIAG, HS_ORDER2 or HS_ORDER4 (or 0)
  *   out          receives a handle that only supports the query calls
  *                (describe/footprint/free); hs_evolve rejects it.
  */
@@ -128,8 +132,13 @@ hs_status hs_factors_info(hs_factors f, int *n_qubits, int *n_factors, int *n_te
                           int *n_diag_terms, int *dtype, double *dt, int *steps);
 /* Term indices of the diagonal factor D, in input order (cap entries max). */
 hs_status hs_diag_terms(hs_factors f, int *term_idx, int cap);
-/* Factor k (application order): whether it carries D, its group size, its
- * number of diagonals, its support bit mask and its stored bytes. */
+/* One step applies the stored factors in this order (factor indices; the
+ * identity order 0..F-1 for first order).  *len receives the length. */
+hs_status hs_step_sequence(hs_factors f, int *seq, int cap, int *len);
+/* time step h of factor k: its exponential is exp(-i h H_k) */
+hs_status hs_factor_step(hs_factors f, int k, double *h);
+/* Factor k: whether it carries D, its group size, its number of diagonals,
+ * its support bit mask and its stored bytes. */
 hs_status hs_factor_info(hs_factors f, int k, int *has_diag, int *n_group_terms,
                          int *n_diags, unsigned long long *support_mask, size_t *bytes);
 hs_status hs_factor_terms(hs_factors f, int k, int *term_idx, int cap);
@@ -143,9 +152,9 @@ hs_status hs_factor_copy_diagonal(hs_factors f, int k, int j, long long start, l
  * diagonals, the caller's states and the library's workspace. */
 hs_status hs_footprint(hs_factors f, int batch, size_t *bytes);
 /* The launches one Trotter step makes for `batch` states with evolve `flags`:
- * *n_launches receives their count; launch i applies factors
- * [first_factor[i], first_factor[i] + n_factors[i]) (arrays of `cap`
- * entries, may be NULL to query the count).  A launch of several factors is
+ * *n_launches receives their count; launch i applies the factors at
+ * step-sequence positions [first_factor[i], first_factor[i] + n_factors[i])
+ * (hs_step_sequence; arrays of `cap` entries, may be NULL to query the count).  A launch of several factors is
  * one fused kernel; batches above HS_MAX_BATCH repeat the list per chunk. */
 hs_status hs_step_launches(hs_factors f, int batch, unsigned flags, int *n_launches,
                            int *first_factor, int *n_factors, int cap);
@@ -222,7 +231,9 @@ hs_status hs_dia_maxabs(hs_dia A, void *stream, double *out);
 /* Alg. 2: X = -i H dt; U = T = I; for k = 1..max_iter: T <- T X / k; stop
  * when max |T_ij| < tol (T not added), else U += T.  A diagonal H takes the
  * exact elementwise exponential.  *n_terms = the number of Taylor terms added
- * after I (0 for diagonal H).  No scaling-and-squaring.  Syncs. */
+ * after I (0 for diagonal H).  No scaling-and-squaring.  Each term's norm is
+ * computed before the term is stored, so the dropped term takes no memory.
+ * Syncs. */
 hs_status hs_spme(hs_dia H, double dt, double tol, int max_iter, void *stream, hs_dia *U,
                   int *n_terms);
 /* Smallest r such that hs_spme(H, t / r, tol, max_iter) has at most `budget`

@@ -16,7 +16,8 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import HS_C64, HS_C128, HS_MERGE_DIAG, HS_NO_FUSE, HS_RENORM, HamsimError  # noqa: F401
+from ._lib import (HS_C64, HS_C128, HS_MERGE_DIAG, HS_NO_FUSE, HS_ORDER2, HS_ORDER4,  # noqa: F401
+                   HS_RENORM, HamsimError)
 
 __all__ = ["Factors", "plan", "build_factors", "evolve", "norm2", "fidelity", "dia_spmv",
            "HamsimError", "dtype_code"]
@@ -95,9 +96,16 @@ class Factors:
             _lib.check(lib.hs_factor_terms(self._h, k, terms, ng.value))
             offs = (ctypes.c_longlong * nd.value)()
             _lib.check(lib.hs_factor_offsets(self._h, k, offs, nd.value))
+            h = ctypes.c_double()
+            _lib.check(lib.hs_factor_step(self._h, k, h))
             out["factors"].append({"has_diag": bool(hd.value), "terms": list(terms)[: ng.value],
                                    "offsets": list(offs), "support_mask": sm.value,
-                                   "bytes": nb.value})
+                                   "bytes": nb.value, "dt": h.value})
+        ln = ctypes.c_int()
+        _lib.check(lib.hs_step_sequence(self._h, None, 0, ln))
+        seq = (ctypes.c_int * max(1, ln.value))()
+        _lib.check(lib.hs_step_sequence(self._h, seq, ln.value, ln))
+        out["sequence"] = list(seq)[: ln.value]
         return out
 
     def copy_diagonal(self, k: int, j: int, offset: int, start: int = 0, count=None,
@@ -132,25 +140,36 @@ class Factors:
         return v.value == 0
 
 
-def plan(strings, coeffs, n, t, steps, budget, merge_diag=True) -> Factors:
+def _build_flags(merge_diag, order):
+    flags = HS_MERGE_DIAG if merge_diag else 0
+    if order == 2:
+        flags |= HS_ORDER2
+    elif order == 4:
+        flags |= HS_ORDER4
+    elif order != 1:
+        raise ValueError("order must be 1, 2 or 4")
+    return flags
+
+
+def plan(strings, coeffs, n, t, steps, budget, merge_diag=True, order=1) -> Factors:
     """Host-only grouping and diagonal sets (no device memory)."""
     lib = _lib.load()
     arr, ri, _keep = _marshal_terms(strings, coeffs, n)
     h = ctypes.c_void_p()
     _lib.check(lib.hs_plan(n, len(ri), arr, ri.ctypes.data, float(t), int(steps), int(budget),
-                           HS_MERGE_DIAG if merge_diag else 0, ctypes.byref(h)))
+                           _build_flags(merge_diag, order), ctypes.byref(h)))
     return Factors(h, built=False)
 
 
 def build_factors(strings, coeffs, n, t, steps, budget, dtype="c64", merge_diag=True,
-                  stream=None) -> Factors:
+                  stream=None, order=1) -> Factors:
+    """Group, plan and build the factors (order 1: Eq. 4; 2: symmetric; 4: Suzuki)."""
     lib = _lib.load()
     arr, ri, _keep = _marshal_terms(strings, coeffs, n)
     h = ctypes.c_void_p()
     _lib.check(lib.hs_build_factors(n, len(ri), arr, ri.ctypes.data, float(t), int(steps),
-                                    int(budget), dtype_code(dtype),
-                                    HS_MERGE_DIAG if merge_diag else 0, _stream_ptr(stream),
-                                    ctypes.byref(h)))
+                                    int(budget), dtype_code(dtype), _build_flags(merge_diag, order),
+                                    _stream_ptr(stream), ctypes.byref(h)))
     return Factors(h, built=True)
 
 

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhamsim.so")
 
 HS_C64, HS_C128 = 0, 1
-HS_MERGE_DIAG, HS_RENORM, HS_NO_FUSE = 1, 2, 4
+HS_MERGE_DIAG, HS_RENORM, HS_NO_FUSE, HS_ORDER2, HS_ORDER4 = 1, 2, 4, 8, 16
 STATUS = {0: "HS_OK", 1: "HS_EINVAL", 2: "HS_ENONHERMITIAN", 3: "HS_EBUDGET",
           4: "HS_ENOMEM", 5: "HS_EDEVICE", 6: "HS_ETOOLARGE"}
 
@@ -32,6 +32,8 @@ _SIG = {
     "hs_factor_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),
                             ctypes.POINTER(ctypes.c_ulonglong), ctypes.POINTER(ctypes.c_size_t)]),
     "hs_factor_terms": (_I, [_P, _I, _P, _I]),
+    "hs_step_sequence": (_I, [_P, _P, _I, ctypes.POINTER(_I)]),
+    "hs_factor_step": (_I, [_P, _I, ctypes.POINTER(_D)]),
     "hs_factor_offsets": (_I, [_P, _I, _P, _I]),
     "hs_factor_copy_diagonal": (_I, [_P, _I, _I, _LL, _LL, _P, _P]),
     "hs_step_launches": (_I, [_P, _I, ctypes.c_uint, ctypes.POINTER(_I), _P, _P, _I]),

@@ -54,7 +54,8 @@ hs_status hip_fail(hipError_t e, const char *what) {
     } while (0)
 
 struct Run {
-    std::vector<int> factors;   // consecutive factor indices
+    int first = 0;              // position of the first factor in the step sequence
+    std::vector<int> factors;   // factor indices at consecutive sequence positions
     Geo geo;
     int launch_batch = 1;       // states per launch (1 when the chunk does not fit)
     bool elementwise = false;   // a single main-diagonal factor
@@ -112,20 +113,23 @@ hs_status make_evolve_plan(hs_factors_s *h, const PlanKey &key, EvolvePlan &ep, 
     ep = EvolvePlan();
     ep.swizzle = key.swizzle;
     const int max_fuse = key.max_fuse;
-    const int F = (int)P.factors.size();
+    // runs are consecutive positions of the step sequence
+    const int F = (int)P.seq.size();
     int f = 0;
     while (f < F) {
         Run run;
-        run.factors.push_back(f);
-        int lb = P.factors[f].xlb, hb = P.factors[f].xhb;
-        bool empty = P.factors[f].xmask_union == 0;
-        if (P.factors[f].offs.size() == 1 && P.factors[f].offs[0] == 0 && empty) {
+        run.first = f;
+        run.factors.push_back(P.seq[f]);
+        const Factor &F0 = P.factors[P.seq[f]];
+        int lb = F0.xlb, hb = F0.xhb;
+        bool empty = F0.xmask_union == 0;
+        if (F0.offs.size() == 1 && F0.offs[0] == 0 && empty) {
             run.elementwise = true;
         }
-        int ndiag = (int)P.factors[f].offs.size();
+        int ndiag = (int)F0.offs.size();
         int g = f + 1;
         while (fuse && g < F && (int)run.factors.size() < max_fuse) {
-            const Factor &G = P.factors[g];
+            const Factor &G = P.factors[P.seq[g]];
             int nlb = lb, nhb = hb;
             if (G.xmask_union) {
                 if (empty) { nlb = G.xlb; nhb = G.xhb; }
@@ -134,7 +138,7 @@ hs_status make_evolve_plan(hs_factors_s *h, const PlanKey &key, EvolvePlan &ep, 
             const Geo geo = geometry(nlb, nhb, n, Tmax);
             const bool good = geo.ok && (geo.qb == 0 || (1 << geo.logW) >= Wmin);
             if (!good || ndiag + (int)G.offs.size() > hs::kMaxDiagsPerLaunch) break;
-            run.factors.push_back(g);
+            run.factors.push_back(P.seq[g]);
             run.elementwise = false;
             ndiag += (int)G.offs.size();
             lb = nlb; hb = nhb;
@@ -281,8 +285,8 @@ static hs_status build_device(hs_factors_s *h, void *stream) {
         temps.push_back(*dst);
         return hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, st);
     };
-    double *phase = nullptr;
     hipError_t e = hipSuccess;
+    void *dzm = nullptr, *dcf = nullptr;
     if (!P.diag.empty()) {
         host_keep.emplace_back();
         host_keep_d.emplace_back();
@@ -292,17 +296,27 @@ static hs_status build_device(hs_factors_s *h, void *stream) {
             zm.push_back(P.terms[k].z);
             cf.push_back(P.terms[k].c);
         }
-        void *dzm = nullptr, *dcf = nullptr;
         if ((e = upload(zm.data(), zm.size() * 8, &dzm)) != hipSuccess ||
-            (e = upload(cf.data(), cf.size() * 8, &dcf)) != hipSuccess ||
-            (e = hipMallocAsync(reinterpret_cast<void **>(&phase), (size_t)P.N * 16, st)) != hipSuccess) {
+            (e = upload(cf.data(), cf.size() * 8, &dcf)) != hipSuccess) {
+            cleanup();
+            return hip_fail(e, "phase table setup");
+        }
+    }
+    // one FP64 phase table exp(-i h E(x)) per distinct time step h of the
+    // factors that carry D
+    std::map<double, double *> phases;
+    for (auto &f : P.factors) {
+        if (!f.has_diag || phases.count(f.dt)) continue;
+        double *phase = nullptr;
+        if ((e = hipMallocAsync(reinterpret_cast<void **>(&phase), (size_t)P.N * 16, st)) != hipSuccess) {
             cleanup();
             return hip_fail(e, "phase table setup");
         }
         temps.push_back(phase);
-        int le = hs::launch_phase_table(P.N, (int)zm.size(), static_cast<uint64_t *>(dzm),
-                                        static_cast<double *>(dcf), P.dt, phase, stream);
+        int le = hs::launch_phase_table(P.N, (int)P.diag.size(), static_cast<uint64_t *>(dzm),
+                                        static_cast<double *>(dcf), f.dt, phase, stream);
         if (le) { cleanup(); return hip_fail((hipError_t)le, "phase table kernel"); }
+        phases[f.dt] = phase;
     }
     for (auto &f : P.factors) {
         hs::ConstructArgs a{};
@@ -334,7 +348,7 @@ static hs_status build_device(hs_factors_s *h, void *stream) {
             a.L = nullptr;
             a.K = 1;
         }
-        a.phase = f.has_diag ? phase : nullptr;
+        a.phase = f.has_diag ? phases[f.dt] : nullptr;
         int le = hs::launch_construct(a, (int)f.offs.size(), P.N, c128, stream);
         if (le) { cleanup(); return hip_fail((hipError_t)le, "construct kernel"); }
     }
@@ -455,6 +469,25 @@ hs_status hs_factor_info(hs_factors f, int k, int *has_diag, int *n_group_terms,
     return HS_OK;
 }
 
+hs_status hs_step_sequence(hs_factors f, int *seq, int cap, int *len) {
+    if (hs_status s = check_handle(f)) return s;
+    const auto &q = f->plan.seq;
+    if (len) *len = (int)q.size();
+    if (seq) {
+        if (cap < (int)q.size()) return fail(HS_EINVAL, "output too small");
+        std::copy(q.begin(), q.end(), seq);
+    }
+    return HS_OK;
+}
+
+hs_status hs_factor_step(hs_factors f, int k, double *h) {
+    const Factor *F = nullptr;
+    if (hs_status s = get_factor(f, k, &F)) return s;
+    if (!h) return fail(HS_EINVAL, "null output");
+    *h = F->dt;
+    return HS_OK;
+}
+
 hs_status hs_factor_terms(hs_factors f, int k, int *term_idx, int cap) {
     const Factor *F = nullptr;
     if (hs_status s = get_factor(f, k, &F)) return s;
@@ -512,7 +545,7 @@ hs_status hs_step_launches(hs_factors f, int batch, unsigned flags, int *n_launc
     if (first_factor && n_factors) {
         if (cap < (int)runs.size()) return fail(HS_EINVAL, "output too small");
         for (size_t i = 0; i < runs.size(); ++i) {
-            first_factor[i] = runs[i].factors.front();
+            first_factor[i] = runs[i].first;
             n_factors[i] = (int)runs[i].factors.size();
         }
     }

@@ -267,22 +267,25 @@ hs_status spme_impl(hs_dia H, double dt, double tol, int max_iter, int cap, hipS
                 if (a + b > -H->N && a + b < H->N) toffs.insert(a + b);
         un.insert(toffs.begin(), toffs.end());
         const double sre = 0.0, sim = -dt / k;        // T_k = T_{k-1} (-i dt H) / k
+        // The stopping test needs only T_k's largest entry: a first pass
+        // computes it without storing T_k, so the final (dropped) term, the
+        // largest one, never occupies memory.  Kept terms are computed again
+        // with storage (same arithmetic, same values).
         double norm = 0.0;
-        if (cap > 0 && (int)un.size() > cap) {
-            hs_status s = spgemm(T, H, sre, sim, false, st, nullptr, &norm);
-            if (s) { delete U; delete T; return s; }
-            if (norm < tol) break;
+        hs_status s = spgemm(T, H, sre, sim, false, st, nullptr, &norm);
+        if (s) { delete U; delete T; return s; }
+        if (norm < tol) break;
+        if (cap > 0 && (int)un.size() > cap) {      // kept and over the budget
             *exceeded = true;
             delete U;
             delete T;
             return HS_OK;
         }
         hs_dia Tn = nullptr;
-        hs_status s = spgemm(T, H, sre, sim, true, st, &Tn, &norm);
+        s = spgemm(T, H, sre, sim, true, st, &Tn, &norm);
         delete T;
         T = Tn;
         if (s) { delete U; return s; }
-        if (norm < tol) break;
         hs_dia Un = nullptr;
         s = dia_sum(U, T, st, &Un);
         if (s) { delete U; delete T; return s; }

@@ -23,6 +23,7 @@ struct Term {
 };
 
 struct Factor {
+    double dt = 0.0;                // time step of this factor's exponential
     bool has_diag = false;          // carries D = exp(-i dt E(x)) on the right
     std::vector<int> terms;         // member term indices (application order)
     std::vector<int64_t> offs;      // ascending diagonal offsets d = col - row
@@ -44,7 +45,9 @@ struct Plan {
     unsigned flags = 0;
     std::vector<Term> terms;
     std::vector<int> diag;          // Z-only term indices
-    std::vector<Factor> factors;    // application order
+    int order = 1;                  // product formula: 1, 2 (symmetric) or 4 (Suzuki)
+    std::vector<Factor> factors;    // distinct stored factors
+    std::vector<int> seq;           // factor indices applied in one step, in order
 };
 
 // Host-side planning (no device calls).  Returns HS_OK or an error with msg.

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <map>
 #include <set>
 
 #include "hs_internal.h"
@@ -173,7 +174,8 @@ hs_status make_plan(int n, int n_terms, const char *const *strings, const double
     if (steps < 1) { msg = "steps must be >= 1"; return HS_EINVAL; }
     if (budget < 1) { msg = "budget must be >= 1"; return HS_EINVAL; }
     if (!std::isfinite(t)) { msg = "t must be finite"; return HS_EINVAL; }
-    if (flags & ~(unsigned)HS_MERGE_DIAG) { msg = "unknown build flag"; return HS_EINVAL; }
+    if (flags & ~(unsigned)(HS_MERGE_DIAG | HS_ORDER2 | HS_ORDER4)) { msg = "unknown build flag"; return HS_EINVAL; }
+    if ((flags & HS_ORDER2) && (flags & HS_ORDER4)) { msg = "choose one product order"; return HS_EINVAL; }
 
     P = Plan();
     P.n = n;
@@ -223,23 +225,67 @@ hs_status make_plan(int n, int n_terms, const char *const *strings, const double
         }
     }
 
-    const bool merge = (flags & HS_MERGE_DIAG) != 0;
-    if (!P.diag.empty() && (!merge || groups.empty())) {
+    auto diag_factor = [&](double h) {
         Factor d;
         d.has_diag = true;
+        d.dt = h;
         d.offs = {0};
         for (int k : P.diag) d.smask |= P.terms[k].z;
-        P.factors.push_back(d);
-    }
-    for (size_t j = 0; j < groups.size(); ++j) {
+        return d;
+    };
+    auto group_factor = [&](const std::vector<int> &g, double h, bool with_diag) {
         Factor f;
-        f.has_diag = merge && j == 0 && !P.diag.empty();
-        f.terms = groups[j];
-        local_unitary(P.terms, f.terms, P.dt, f.bits, f.L);
+        f.has_diag = with_diag;
+        f.dt = h;
+        f.terms = g;
+        local_unitary(P.terms, f.terms, h, f.bits, f.L);
         f.offs = offsets_of(f.bits, f.L);
         for (int q : f.bits) f.smask |= 1ull << q;
         for (int k : f.terms) f.xmask_union |= P.terms[k].x;
-        P.factors.push_back(f);
+        return f;
+    };
+    P.order = (flags & HS_ORDER4) ? 4 : (flags & HS_ORDER2) ? 2 : 1;
+    if (P.order == 1) {
+        const bool merge = (flags & HS_MERGE_DIAG) != 0;
+        if (!P.diag.empty() && (!merge || groups.empty())) P.factors.push_back(diag_factor(P.dt));
+        for (size_t j = 0; j < groups.size(); ++j)
+            P.factors.push_back(group_factor(groups[j], P.dt, merge && j == 0 && !P.diag.empty()));
+        for (size_t k = 0; k < P.factors.size(); ++k) P.seq.push_back((int)k);
+    } else {
+        // Symmetric products over F = (D, G_1, ..., G_m): S2(h) applies
+        // F_1..F_{L-1} with h/2, F_L with h, then F_{L-1}..F_1 with h/2;
+        // S4(dt) = S2(p dt) S2(p dt) S2((1-4p) dt) S2(p dt) S2(p dt),
+        // p = 1/(4 - 4^(1/3)).  D stays a factor of its own; every distinct
+        // (factor, time step) pair is stored once.
+        const int L = (P.diag.empty() ? 0 : 1) + (int)groups.size();
+        std::vector<std::pair<int, double>> seq;     // (F index, h); F index 0 = D when present
+        auto s2 = [&](double h) {
+            if (L == 1) { seq.push_back({0, h}); return; }
+            for (int j = 0; j < L - 1; ++j) seq.push_back({j, h / 2});
+            seq.push_back({L - 1, h});
+            for (int j = L - 2; j >= 0; --j) seq.push_back({j, h / 2});
+        };
+        if (P.order == 2) {
+            s2(P.dt);
+        } else {
+            const double p = 1.0 / (4.0 - std::pow(4.0, 1.0 / 3.0));
+            s2(p * P.dt);
+            s2(p * P.dt);
+            s2((1 - 4 * p) * P.dt);
+            s2(p * P.dt);
+            s2(p * P.dt);
+        }
+        std::map<std::pair<int, double>, int> made;
+        for (auto &e : seq) {
+            auto it = made.find(e);
+            if (it == made.end()) {
+                const bool is_diag = !P.diag.empty() && e.first == 0;
+                const int g = e.first - (P.diag.empty() ? 0 : 1);
+                P.factors.push_back(is_diag ? diag_factor(e.second) : group_factor(groups[g], e.second, false));
+                it = made.emplace(e, (int)P.factors.size() - 1).first;
+            }
+            P.seq.push_back(it->second);
+        }
     }
     for (auto &f : P.factors) {
         if (f.xmask_union) {

@@ -332,3 +332,35 @@ def test_merge_flag_does_not_change_the_result():
         outs.append(p.cpu().numpy()[0])
         f.close()
     assert np.abs(outs[0] - outs[1]).max() <= 1e-13
+
+
+# ------------------------------------------------------------------ higher-order products
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_higher_order_products_match_oracle(order):
+    hs, torch = hs_gpu()
+    from oracle import evolve as oev
+    note(f"order {order}: config1 c128 and config2 c64")
+    H = config_hamiltonian(1)
+    terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
+    part = ofac.first_fit(terms, 8, 0.1)
+    f = hs.build_factors(H.strings, H.coeffs, 8, 1.0, 10, 8, dtype="c128", order=order)
+    p = _to_dev(torch, ws.zero_state(8)[None], np.complex128)
+    hs.evolve(f, p, 10)
+    ref = oev.evolve(terms, part, ws.zero_state(8), 8, 0.1, 10, order=order)
+    assert np.abs(p.cpu().numpy()[0] - ref).max() <= 1e-12
+    # fused and unfused launches agree bit for bit
+    q = _to_dev(torch, ws.zero_state(8)[None], np.complex128)
+    hs.evolve(f, q, 10, fuse=False)
+    assert np.array_equal(p.cpu().numpy(), q.cpu().numpy())
+    f.close()
+    H = config_hamiltonian(2)
+    terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
+    part = ofac.first_fit(terms, 16, 0.02)
+    f = hs.build_factors(H.strings, H.coeffs, 20, 2.0, 100, 16, dtype="c64", order=order)
+    p = _to_dev(torch, ws.neel_state(20, np.complex64)[None], np.complex64)
+    hs.evolve(f, p, 20)
+    ref = oev.evolve(terms, part, ws.neel_state(20), 20, 0.02, 20, order=order, threads=oracle_threads())
+    assert fid(p.cpu().numpy()[0].astype(np.complex128), ref) >= 1 - 1e-6
+    assert f.check_closure()
+    f.close()

@@ -59,7 +59,7 @@ def _check_plan_matches_oracle(hs, H, budget, t, steps, merge=True):
         assert got["terms"] == g
         assert got["offsets"] == ofac.factor_offsets(terms, (has_diag, g), t / steps)
         # bytes: every diagonal N-|d| complex64 entries, each start 256-byte aligned
-        exp = sum(-(-(H.n and (1 << H.n) - abs(d)) // 32) * 32 * 8 for d in got["offsets"])
+        exp = sum((((1 << H.n) - abs(d) + 31) // 32) * 32 * 8 for d in got["offsets"])
         assert got["bytes"] == exp
     f.close()
 
@@ -139,3 +139,28 @@ def test_footprint_counts_diagonals_states_and_workspace(hs):
     assert abs(diag_bytes - 120.5 * N * 8) < 64 * 256
     fp1, fp8 = f.footprint(1), f.footprint(8)
     assert fp1 >= diag_bytes + N * 8 and fp8 - fp1 == 7 * N * 8
+
+
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_higher_order_plan_matches_oracle_sequence(hs, cfg, order):
+    from oracle import evolve as oev
+    H = config_hamiltonian(cfg)
+    run = wh.CONFIG_RUN[cfg]
+    dt = run["t"] / run["steps"]
+    f = hs.plan(H.strings, H.coeffs, H.n, run["t"], run["steps"], run["budget"], order=order)
+    desc = f.describe()
+    terms, part = _oracle_partition(H, run["budget"], run["t"], run["steps"])
+    seq = oev.product_sequence(part, dt, order)
+    assert len(desc["sequence"]) == len(seq)
+    for k, (g, h) in zip(desc["sequence"], seq):
+        fac = desc["factors"][k]
+        assert fac["dt"] == h                       # bit-equal time steps
+        assert fac["has_diag"] == (g < 0)
+        assert fac["terms"] == ([] if g < 0 else part.groups[g])
+        grp = [] if g < 0 else part.groups[g]
+        assert fac["offsets"] == ofac.factor_offsets(terms, (g < 0, grp), h)
+    # each distinct (factor, step) pair is stored once
+    pairs = {(g, h) for g, h in seq}
+    assert len(desc["factors"]) == len(pairs)
+    f.close()

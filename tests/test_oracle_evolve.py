@@ -229,3 +229,58 @@ def test_planted_mistakes_fail_the_pins(monkeypatch, mutant):
             return oev.evolve_np(terms, factors.Partition(part.diag, [g[:-1] or g for g in part.groups]),
                                  psi0, n, dt, r)
     assert not _pin_holds(terms, part, 5, dt, r, psi0, fn)
+
+
+# ------------------------------------------------- higher-order products
+
+def _expm_sequence(terms, part, n, dt, r, psi0, order):
+    step = np.eye(1 << n, dtype=np.complex128)
+    for g, h in oev.product_sequence(part, dt, order):
+        idx = part.diag if g < 0 else part.groups[g]
+        step = sl.expm(-1j * h * pauli.dense_hamiltonian([terms[k] for k in idx], n)) @ step
+    return np.linalg.matrix_power(step, r) @ psi0
+
+
+def test_product_sequences_are_symmetric():
+    part = factors.Partition([0, 1], [[2], [3, 4], [5]])
+    s2 = oev.product_sequence(part, 0.1, 2)
+    assert [g for g, _ in s2] == [-1, 0, 1, 2, 1, 0, -1]
+    assert [h for _, h in s2] == [0.05, 0.05, 0.05, 0.1, 0.05, 0.05, 0.05]
+    s4 = oev.product_sequence(part, 0.1, 4)
+    assert len(s4) == 5 * len(s2)
+    p = oev.SUZUKI_P
+    assert abs(4 * p + (1 - 4 * p) - 1.0) < 1e-15
+    # the total time each factor receives per step is dt
+    for seq in (s2, s4):
+        for g in (-1, 0, 1, 2):
+            assert abs(sum(h for q, h in seq if q == g) - 0.1) < 1e-15
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_higher_order_equals_expm_products_and_numpy_twin(oracle_lib, order):
+    H = _heis(5)
+    dt, r = 0.17, 3
+    terms, part = _setup(H, 16, dt)
+    psi0 = _rand_state(5, 3)
+    got = oev.evolve(terms, part, psi0, 5, dt, r, order=order)
+    assert np.abs(got - _expm_sequence(terms, part, 5, dt, r, psi0, order)).max() < 1e-12
+    assert np.abs(got - oev.evolve_np(terms, part, psi0, 5, dt, r, order=order)).max() < 1e-13
+
+
+@pytest.mark.parametrize("order,ratio,rs", [(2, 4.0, (8, 16, 32, 64)), (4, 16.0, (4, 8, 16, 32))])
+def test_higher_order_error_scaling(oracle_lib, order, ratio, rs):
+    n, t = 7, 1.0
+    H = wh.tfim_1d(n, 1.0, 1.0)
+    Hd = pauli.dense_hamiltonian(pauli.parse_terms(H.strings, H.coeffs, n), n)
+    psi0 = _rand_state(n, 21)
+    exact = sl.expm(-1j * t * Hd) @ psi0
+    errs = []
+    for r in rs:
+        terms, part = _setup(H, 8, t / r)
+        errs.append(np.linalg.norm(oev.evolve(terms, part, psi0, n, t / r, r, order=order) - exact))
+    q = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    assert abs(q[-1] - ratio) < 0.1 * ratio, q
+    # and far below the first-order error at the same r
+    terms, part = _setup(H, 8, t / rs[-1])
+    e1 = np.linalg.norm(oev.evolve(terms, part, psi0, n, t / rs[-1], rs[-1]) - exact)
+    assert errs[-1] < e1 / 10
