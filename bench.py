@@ -51,10 +51,12 @@ def kernel_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def launch_bytes(desc, launches, N, batch, elem):
-    """Algorithmic bytes of each launch of one step."""
+def launch_bytes(desc, launches, N, batch, elem, seq=None):
+    """Algorithmic bytes of each launch of one step (`seq`: the factor
+    sequence the launch positions index; the lone step by default)."""
     out = []
-    seq = desc.get("sequence") or list(range(len(desc["factors"])))
+    if seq is None:
+        seq = desc.get("sequence") or list(range(len(desc["factors"])))
     for first, cnt in launches:
         facs = [desc["factors"][k] for k in seq[first:first + cnt]]
         coef = sum((N - abs(d)) * elem for f in facs for d in f["offsets"])
@@ -344,6 +346,52 @@ def other_configs(torch, steps=10, warmup=2):
     return out
 
 
+def higher_order_leg(torch, steps=10, warmup=3):
+    """The symmetric second-order and fourth-order Suzuki products on the
+    n = 26 2-D TFIM (complex64, budget 16), timed as one evolution of `steps`
+    steps so that steps meet in the joint factor.  Algorithmic bytes: every
+    launch's coefficient diagonals plus the state read and written, summed
+    over the first, middle and last steps' launch lists."""
+    import paper_2606_16959_amd as hs
+    from workloads import config_hamiltonian, states as ws
+    from workloads.hamiltonians import CONFIG_RUN
+    H = config_hamiltonian(3)
+    run = CONFIG_RUN[3]
+    N = 1 << H.n
+    out = []
+    for order in (2, 4):
+        f = hs.build_factors(H.strings, H.coeffs, H.n, run["t"], run["steps"], run["budget"],
+                             dtype="c64", order=order)
+        desc = f.describe()
+        parts = {p: launch_bytes(desc, f.step_launches(1, part=p), N, 1, 8, f.part_sequence(p, desc))
+                 for p in (1, 2, 3)}
+        nbytes = sum(parts[1]) + (steps - 2) * sum(parts[2]) + sum(parts[3])
+        n_launch = len(parts[1]) + (steps - 2) * len(parts[2]) + len(parts[3])
+        psi = torch.from_numpy(np.ascontiguousarray(ws.config_states(3, np.complex64))).cuda()
+        hs.evolve(f, psi, warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        hs.evolve(f, psi, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        row = {"workload": "tfim2d_5x5_plus1_n26", "order": order, "dtype": "c64",
+               "stored_factors": len(desc["factors"]),
+               "factor_gb": round(sum(x["bytes"] for x in desc["factors"]) / 1e9, 2),
+               "factors_per_step": len(f.part_sequence(2, desc)),
+               "launches_per_step": round(n_launch / steps, 2), "ms_per_step": round(ms, 3),
+               "gb_per_step": round(nbytes / steps / 1e9, 2),
+               "gbs": round(nbytes / steps / ms / 1e6, 1)}
+        row["frac_of_peak"] = round(row["gbs"] / HBM_PEAK_GBS, 4)
+        out.append(row)
+        log(f"order {order}: {ms:.3f} ms/step {row['gbs']} GB/s {row['launches_per_step']} launches/step")
+        f.close()
+        del psi
+        torch.cuda.empty_cache()
+    return out
+
+
 def write_serve_summary(stats, command, fname):
     md = ["# Served stream: mixed TFIM / Heisenberg / MaxCut / TSP jobs, n in [10, 24], complex64", "",
           f"Command (repository root, GPU box): `{command}`", "",
@@ -534,6 +582,7 @@ def main():
         f.close()
         torch.cuda.empty_cache()
         others = other_configs(torch)
+        others.append({"higher_order": higher_order_leg(torch)})
         others.append({"single_propagator": single_propagator_leg(torch)})
     serve = None
     if args.serve_jobs > 0:

@@ -133,8 +133,18 @@ hs_status hs_factors_info(hs_factors f, int *n_qubits, int *n_factors, int *n_te
 /* Term indices of the diagonal factor D, in input order (cap entries max). */
 hs_status hs_diag_terms(hs_factors f, int *term_idx, int cap);
 /* One step applies the stored factors in this order (factor indices; the
- * identity order 0..F-1 for first order).  *len receives the length. */
+ * identity order 0..F-1 for first order).  *len receives the length.  For
+ * orders 2 and 4, neighbours that share a generator are already combined
+ * (their time steps add), e.g. the junctions F_1(p dt/2) F_1(p dt/2) of the
+ * fourth-order product. */
 hs_status hs_step_sequence(hs_factors f, int *seq, int cap, int *len);
+/* The joint factor of a symmetric product, or -1 (first order, or a step of
+ * one factor).  A symmetric step s_0 .. s_{L-1} starts and ends with the same
+ * generator, so where two steps meet, hs_evolve applies s_{L-1} s_0 as the
+ * one stored factor *factor whose time step is the sum of theirs: `steps`
+ * steps apply s_0 .. s_{L-2} J, then (s_1 .. s_{L-2} J) steps-2 times, then
+ * s_1 .. s_{L-1}; one step applies the sequence as it is. */
+hs_status hs_step_joint(hs_factors f, int *factor);
 /* time step h of factor k: its exponential is exp(-i h H_k) */
 hs_status hs_factor_step(hs_factors f, int k, double *h);
 /* Factor k: whether it carries D, its group size, its number of diagonals,
@@ -153,10 +163,15 @@ hs_status hs_factor_copy_diagonal(hs_factors f, int k, int j, long long start, l
 hs_status hs_footprint(hs_factors f, int batch, size_t *bytes);
 /* The launches one Trotter step makes for `batch` states with evolve `flags`:
  * *n_launches receives their count; launch i applies the factors at
- * step-sequence positions [first_factor[i], first_factor[i] + n_factors[i])
- * (hs_step_sequence; arrays of `cap` entries, may be NULL to query the count).  A launch of several factors is
- * one fused kernel; batches above HS_MAX_BATCH repeat the list per chunk. */
-hs_status hs_step_launches(hs_factors f, int batch, unsigned flags, int *n_launches,
+ * positions [first_factor[i], first_factor[i] + n_factors[i]) of the part's
+ * factor sequence (arrays of `cap` entries, may be NULL to query the count).
+ * `part` selects the step: 0 a lone step (the sequence of hs_step_sequence),
+ * and of an evolution of several steps 1 the first (s_0 .. s_{L-2} J),
+ * 2 a middle one (s_1 .. s_{L-2} J), 3 the last (s_1 .. s_{L-1}), with J the
+ * joint factor (hs_step_joint); without a joint all four are the plain step.
+ * A launch of several factors is one fused kernel; batches above
+ * HS_MAX_BATCH repeat the list per chunk. */
+hs_status hs_step_launches(hs_factors f, int batch, unsigned flags, int part, int *n_launches,
                            int *first_factor, int *n_factors, int cap);
 /* Sets *violated to 1 if any in-place launch met a nonzero coefficient that
  * couples rows of different tiles (never for factors built here); syncs. */
@@ -241,7 +256,10 @@ hs_status hs_spme(hs_dia H, double dt, double tol, int max_iter, void *stream, h
  * meets the budget, otherwise doubling u = 2, 4, ... until it does, then
  * bisection between the last failing and the first passing value.  A probe
  * stops as soon as a Taylor term above the tolerance would push the count
- * past the budget, without storing that term.  HS_EBUDGET above 2^24.  Syncs. */
+ * past the budget.  The probes share one sequence of powers of H: term k at
+ * step dt has largest entry |dt|^k / k! max|H^k| and H^k's offsets, so each
+ * power is formed once (and stored only while its offsets fit the budget).
+ * H must be complex128.  HS_EBUDGET above 2^24.  Syncs. */
 hs_status hs_estimate_timesteps(hs_dia H, double t, int budget, double tol, int max_iter,
                                 void *stream, int *steps);
 /* complex64 copy of a complex128 operator (round to nearest); syncs */

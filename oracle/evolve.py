@@ -91,6 +91,19 @@ def product_sequence(partition: Partition, dt: float, order: int = 1) -> list:
     raise ValueError(f"order {order} not supported")
 
 
+def merge_adjacent(seq: list) -> list:
+    """Combine neighbouring entries of the same factor: exp(-i a G) exp(-i b G)
+    = exp(-i (a + b) G) exactly, since G commutes with itself.  Time steps add
+    left to right."""
+    out = []
+    for g, h in seq:
+        if out and out[-1][0] == g:
+            out[-1] = (g, out[-1][1] + h)
+        else:
+            out.append((g, h))
+    return out
+
+
 def evolve(terms, partition: Partition, psi: np.ndarray, n: int, dt: float, steps: int,
            threads: int = 0, order: int = 1) -> np.ndarray:
     """Return psi_r for a [N] or [B, N] state (a new complex128 array)."""

@@ -106,6 +106,9 @@ class Factors:
         seq = (ctypes.c_int * max(1, ln.value))()
         _lib.check(lib.hs_step_sequence(self._h, seq, ln.value, ln))
         out["sequence"] = list(seq)[: ln.value]
+        j = ctypes.c_int()
+        _lib.check(lib.hs_step_joint(self._h, j))
+        out["joint"] = j.value
         return out
 
     def copy_diagonal(self, k: int, j: int, offset: int, start: int = 0, count=None,
@@ -118,16 +121,30 @@ class Factors:
                                                        out.ctypes.data, _stream_ptr(stream)))
         return out
 
-    def step_launches(self, batch: int = 1, fuse: bool = True) -> list:
-        """[(first_factor, n_factors)] of the launches of one Trotter step."""
+    def step_launches(self, batch: int = 1, fuse: bool = True, part: int = 0) -> list:
+        """[(first, n_factors)] of the launches of one Trotter step: positions
+        in the part's factor sequence (:meth:`part_sequence`)."""
         lib = _lib.load()
         n = ctypes.c_int()
         flags = 0 if fuse else HS_NO_FUSE
-        _lib.check(lib.hs_step_launches(self._h, batch, flags, n, None, None, 0))
+        _lib.check(lib.hs_step_launches(self._h, batch, flags, part, n, None, None, 0))
         first = (ctypes.c_int * max(1, n.value))()
         cnt = (ctypes.c_int * max(1, n.value))()
-        _lib.check(lib.hs_step_launches(self._h, batch, flags, n, first, cnt, n.value))
+        _lib.check(lib.hs_step_launches(self._h, batch, flags, part, n, first, cnt, n.value))
         return [(first[i], cnt[i]) for i in range(n.value)]
+
+    def part_sequence(self, part: int = 0, desc: dict | None = None) -> list:
+        """Factor indices one step applies: part 0 a lone step, 1/2/3 the
+        first/middle/last step of several (differ only with a joint factor)."""
+        d = desc or self.describe()
+        seq, j = d["sequence"], d["joint"]
+        if j < 0 or part == 0:
+            return list(seq)
+        if part == 1:
+            return seq[:-1] + [j]
+        if part == 2:
+            return seq[1:-1] + [j]
+        return seq[1:]
 
     def footprint(self, batch: int = 1) -> int:
         b = ctypes.c_size_t()

@@ -63,9 +63,27 @@ struct Run {
     std::vector<int> dstart;    // per factor, relative to desc_start (size nf + 1)
 };
 
+// The factor sequence of each part of an evolution of several steps.  With a
+// joint factor J the steps of a symmetric product run s_0 .. s_{L-2} J, then
+// (s_1 .. s_{L-2} J) for the middle steps, then s_1 .. s_{L-1}; part 0 is a
+// lone step.  Without a joint every part is the plain step.
+enum { kPartLone = 0, kPartFirst = 1, kPartMiddle = 2, kPartLast = 3, kParts = 4 };
+
+std::vector<int> part_sequence(const Plan &P, int part) {
+    const auto &q = P.seq;
+    if (P.joint < 0 || part == kPartLone) return q;
+    std::vector<int> out;
+    const size_t L = q.size();
+    const size_t a = part == kPartFirst ? 0 : 1;
+    const size_t b = part == kPartLast ? L : L - 1;
+    for (size_t i = a; i < b; ++i) out.push_back(q[i]);
+    if (part != kPartLast) out.push_back(P.joint);
+    return out;
+}
+
 struct EvolvePlan {
     int swizzle = 0;
-    std::vector<Run> runs;
+    std::vector<Run> runs[kParts];
     std::vector<DiagDesc> host_desc;
     DiagDesc *dev_desc = nullptr;
 };
@@ -113,66 +131,71 @@ hs_status make_evolve_plan(hs_factors_s *h, const PlanKey &key, EvolvePlan &ep, 
     ep = EvolvePlan();
     ep.swizzle = key.swizzle;
     const int max_fuse = key.max_fuse;
-    // runs are consecutive positions of the step sequence
-    const int F = (int)P.seq.size();
-    int f = 0;
-    while (f < F) {
-        Run run;
-        run.first = f;
-        run.factors.push_back(P.seq[f]);
-        const Factor &F0 = P.factors[P.seq[f]];
-        int lb = F0.xlb, hb = F0.xhb;
-        bool empty = F0.xmask_union == 0;
-        if (F0.offs.size() == 1 && F0.offs[0] == 0 && empty) {
-            run.elementwise = true;
-        }
-        int ndiag = (int)F0.offs.size();
-        int g = f + 1;
-        while (fuse && g < F && (int)run.factors.size() < max_fuse) {
-            const Factor &G = P.factors[P.seq[g]];
-            int nlb = lb, nhb = hb;
-            if (G.xmask_union) {
-                if (empty) { nlb = G.xlb; nhb = G.xhb; }
-                else { nlb = std::min(lb, G.xlb); nhb = std::max(hb, G.xhb); }
+    for (int part = 0; part < (P.joint < 0 ? 1 : kParts); ++part) {
+        // runs are consecutive positions of the part's factor sequence
+        const std::vector<int> seq = part_sequence(P, part);
+        std::vector<Run> &runs = ep.runs[part];
+        const int F = (int)seq.size();
+        int f = 0;
+        while (f < F) {
+            Run run;
+            run.first = f;
+            run.factors.push_back(seq[f]);
+            const Factor &F0 = P.factors[seq[f]];
+            int lb = F0.xlb, hb = F0.xhb;
+            bool empty = F0.xmask_union == 0;
+            if (F0.offs.size() == 1 && F0.offs[0] == 0 && empty) {
+                run.elementwise = true;
             }
-            const Geo geo = geometry(nlb, nhb, n, Tmax);
-            const bool good = geo.ok && (geo.qb == 0 || (1 << geo.logW) >= Wmin);
-            if (!good || ndiag + (int)G.offs.size() > hs::kMaxDiagsPerLaunch) break;
-            run.factors.push_back(P.seq[g]);
-            run.elementwise = false;
-            ndiag += (int)G.offs.size();
-            lb = nlb; hb = nhb;
-            if (G.xmask_union) empty = false;
-            ++g;
-        }
-        run.launch_batch = batch;
-        run.geo = geometry(empty ? 0 : lb, empty ? 0 : hb, n, Tmax);
-        if (!run.geo.ok) {            // orbit wider than the batched tile: one state per launch
-            run.launch_batch = 1;
-            run.geo = geometry(lb, hb, n, tile_rows_max(h->dtype, 1));
-            if (!run.geo.ok) return fail(HS_ETOOLARGE, "factor coupling range does not fit a tile");
-        }
-        run.desc_start = (int)ep.host_desc.size();
-        run.dstart.push_back(0);
-        for (int k : run.factors) {
-            const Factor &Fk = P.factors[k];
-            for (size_t j = 0; j < Fk.offs.size(); ++j) {
-                const int64_t d = Fk.offs[j];
-                DiagDesc dd{};
-                dd.ptr = static_cast<const char *>(Fk.dev) + Fk.elem_off[j] * sc;
-                dd.off = (int32_t)d;
-                const int64_t lowmask = (int64_t(1) << run.geo.qb) - 1;
-                dd.regular = (d & lowmask) == 0;
-                dd.m = dd.regular ? (int32_t)(d >> run.geo.qb) : 0;
-                dd.lo = (int32_t)std::max<int64_t>(0, -d);
-                dd.hi = (int32_t)std::min<int64_t>(P.N, P.N - d);
-                ep.host_desc.push_back(dd);
+            int ndiag = (int)F0.offs.size();
+            int g = f + 1;
+            while (fuse && g < F && (int)run.factors.size() < max_fuse) {
+                const Factor &G = P.factors[seq[g]];
+                int nlb = lb, nhb = hb;
+                if (G.xmask_union) {
+                    if (empty) { nlb = G.xlb; nhb = G.xhb; }
+                    else { nlb = std::min(lb, G.xlb); nhb = std::max(hb, G.xhb); }
+                }
+                const Geo geo = geometry(nlb, nhb, n, Tmax);
+                const bool good = geo.ok && (geo.qb == 0 || (1 << geo.logW) >= Wmin);
+                if (!good || ndiag + (int)G.offs.size() > hs::kMaxDiagsPerLaunch) break;
+                run.factors.push_back(seq[g]);
+                run.elementwise = false;
+                ndiag += (int)G.offs.size();
+                lb = nlb; hb = nhb;
+                if (G.xmask_union) empty = false;
+                ++g;
             }
-            run.dstart.push_back((int)(ep.host_desc.size() - run.desc_start));
+            run.launch_batch = batch;
+            run.geo = geometry(empty ? 0 : lb, empty ? 0 : hb, n, Tmax);
+            if (!run.geo.ok) {            // orbit wider than the batched tile: one state per launch
+                run.launch_batch = 1;
+                run.geo = geometry(lb, hb, n, tile_rows_max(h->dtype, 1));
+                if (!run.geo.ok) return fail(HS_ETOOLARGE, "factor coupling range does not fit a tile");
+            }
+            run.desc_start = (int)ep.host_desc.size();
+            run.dstart.push_back(0);
+            for (int k : run.factors) {
+                const Factor &Fk = P.factors[k];
+                for (size_t j = 0; j < Fk.offs.size(); ++j) {
+                    const int64_t d = Fk.offs[j];
+                    DiagDesc dd{};
+                    dd.ptr = static_cast<const char *>(Fk.dev) + Fk.elem_off[j] * sc;
+                    dd.off = (int32_t)d;
+                    const int64_t lowmask = (int64_t(1) << run.geo.qb) - 1;
+                    dd.regular = (d & lowmask) == 0;
+                    dd.m = dd.regular ? (int32_t)(d >> run.geo.qb) : 0;
+                    dd.lo = (int32_t)std::max<int64_t>(0, -d);
+                    dd.hi = (int32_t)std::min<int64_t>(P.N, P.N - d);
+                    ep.host_desc.push_back(dd);
+                }
+                run.dstart.push_back((int)(ep.host_desc.size() - run.desc_start));
+            }
+            runs.push_back(run);
+            f = g;
         }
-        ep.runs.push_back(run);
-        f = g;
     }
+    for (int part = 1; P.joint < 0 && part < kParts; ++part) ep.runs[part] = ep.runs[0];
     const size_t bytes = ep.host_desc.size() * sizeof(DiagDesc);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     HS_HIP(hipMallocAsync(reinterpret_cast<void **>(&ep.dev_desc), std::max<size_t>(bytes, 64), st),
@@ -411,9 +434,12 @@ hs_status hs_evolve(hs_factors f, void *psi, int batch, int steps, void *stream,
         void *p = static_cast<char *>(psi) + (size_t)c0 * P.N * sc;
         const double *rec = f->records() + 2;    // squared norm of state b at rec[4 b]
         for (int s = 0; s < steps; ++s) {
-            for (size_t ri = 0; ri < ep.runs.size(); ++ri) {
+            const int part = steps == 1 ? kPartLone
+                             : s == 0 ? kPartFirst : s == steps - 1 ? kPartLast : kPartMiddle;
+            const std::vector<Run> &runs = ep.runs[part];
+            for (size_t ri = 0; ri < runs.size(); ++ri) {
                 const double *nrm = (renorm && s > 0 && ri == 0) ? rec : nullptr;
-                if (hs_status st = launch_run(f, ep, ep.runs[ri], p, chunk, nrm, stream)) return st;
+                if (hs_status st = launch_run(f, ep, runs[ri], p, chunk, nrm, stream)) return st;
             }
             if (renorm) {
                 int e = hs::launch_reduce(p, f->dtype, p, f->dtype, chunk, P.N, f->partials(),
@@ -480,6 +506,13 @@ hs_status hs_step_sequence(hs_factors f, int *seq, int cap, int *len) {
     return HS_OK;
 }
 
+hs_status hs_step_joint(hs_factors f, int *factor) {
+    if (hs_status s = check_handle(f)) return s;
+    if (!factor) return fail(HS_EINVAL, "null output");
+    *factor = f->plan.joint;
+    return HS_OK;
+}
+
 hs_status hs_factor_step(hs_factors f, int k, double *h) {
     const Factor *F = nullptr;
     if (hs_status s = get_factor(f, k, &F)) return s;
@@ -523,11 +556,12 @@ hs_status hs_factor_copy_diagonal(hs_factors f, int k, int j, long long start, l
     return HS_OK;
 }
 
-hs_status hs_step_launches(hs_factors f, int batch, unsigned flags, int *n_launches,
+hs_status hs_step_launches(hs_factors f, int batch, unsigned flags, int part, int *n_launches,
                            int *first_factor, int *n_factors, int cap) {
     if (hs_status s = check_handle(f)) return s;
     if (!f->built) return fail(HS_EINVAL, "handle was planned, not built");
     if (batch < 1 || !n_launches) return fail(HS_EINVAL, "batch >= 1 and an output are required");
+    if (part < 0 || part >= kParts) return fail(HS_EINVAL, "part must be 0..3");
     if (flags & ~(unsigned)(HS_RENORM | HS_NO_FUSE)) return fail(HS_EINVAL, "unknown evolve flag");
     std::lock_guard<std::mutex> lock(f->mu);
     const int chunk = std::min(HS_MAX_BATCH, batch);
@@ -540,7 +574,7 @@ hs_status hs_step_launches(hs_factors f, int batch, unsigned flags, int *n_launc
         it = f->plans.emplace(key, std::move(ep)).first;
         HS_HIP(hipStreamSynchronize(f->alloc_stream), "hipStreamSynchronize");
     }
-    const auto &runs = it->second.runs;
+    const auto &runs = it->second.runs[part];
     *n_launches = (int)runs.size();
     if (first_factor && n_factors) {
         if (cap < (int)runs.size()) return fail(HS_EINVAL, "output too small");

@@ -499,41 +499,99 @@ hs_status hs_spme(hs_dia H, double dt, double tol, int max_iter, void *stream, h
 
 hs_status hs_estimate_timesteps(hs_dia H, double t, int budget, double tol, int max_iter, void *stream,
                                 int *steps) {
-    if (!H || !steps || budget < 1 || !(tol > 0.0) || max_iter < 1) return dfail(HS_EINVAL, "bad arguments");
+    if (!H || !steps || budget < 1 || !(tol > 0.0) || max_iter < 1 || !std::isfinite(t))
+        return dfail(HS_EINVAL, "bad arguments");
+    if (H->dtype != HS_C128) return dfail(HS_EINVAL, "the exponential needs a complex128 operator");
     if (H->offs.size() == 1 && H->offs[0] == 0) {
         *steps = 1;
         return HS_OK;
     }
     hipStream_t st = S(stream);
-    auto ok = [&](long long r, bool *res) -> hs_status {
-        hs_dia U = nullptr;
-        int K = 0;
-        bool exceeded = false;
-        hs_status s = spme_impl(H, t / (double)r, tol, max_iter, budget, st, &U, &K, &exceeded);
-        if (s) return s;
-        *res = !exceeded && U && (int)U->offs.size() <= budget;
-        delete U;
+    // Taylor term k at step dt is T_k = (-i dt)^k H^k / k!: its largest entry
+    // is |dt|^k / k! * max|H^k| and its structural offsets are H^k's, so one
+    // sequence of powers of H serves every probe of the search.  max|H^k|
+    // comes from a pass that stores nothing; H^(k-1) is stored only when a
+    // probe reaches term k with the count so far within the budget, so a
+    // stored power never holds more than `budget` diagonals.
+    std::vector<double> mk{0.0};                    // mk[k] = max |H^k|
+    std::vector<size_t> uk{1};                      // uk[k] = |offsets of H^0 .. H^k|
+    std::set<int64_t> un{0};
+    std::vector<int64_t> poffs{0};                  // structural offsets of H^(mk.size() - 1)
+    hs_dia P = H;                                   // H^p, owned when p >= 2
+    int p = 1;
+    auto release = [&]() {
+        if (P != H) delete P;
+        P = nullptr;
+    };
+    auto power = [&](int k) -> hs_status {          // extend the tables to term k
+        while ((int)mk.size() <= k) {
+            const int j = (int)mk.size();
+            double m = 0.0;
+            if (j == 1) {
+                if (hs_status s = hs_dia_maxabs(H, st, &m)) return s;
+            } else {
+                while (p < j - 1) {                 // H^(p+1), within the budget (see above)
+                    hs_dia Pn = nullptr;
+                    double unused = 0.0;
+                    if (hs_status s = spgemm(P, H, 1.0, 0.0, true, st, &Pn, &unused)) return s;
+                    if (P != H) delete P;
+                    P = Pn;
+                    ++p;
+                }
+                if (hs_status s = spgemm(P, H, 1.0, 0.0, false, st, nullptr, &m)) return s;
+            }
+            std::set<int64_t> nx;
+            for (int64_t a : poffs)
+                for (int64_t b : H->offs)
+                    if (a + b > -H->N && a + b < H->N) nx.insert(a + b);
+            poffs.assign(nx.begin(), nx.end());
+            un.insert(nx.begin(), nx.end());
+            mk.push_back(m);
+            uk.push_back(un.size());
+        }
         return HS_OK;
     };
-    bool f = false;
-    long long lo = 1;
-    if (hs_status s = ok(lo, &f)) return s;
-    if (f) { *steps = 1; return HS_OK; }
-    long long u = 2;
-    for (;;) {
-        if (hs_status s = ok(u, &f)) return s;
-        if (f) break;
-        lo = u;
-        u *= 2;
-        if (u > (1ll << 24)) return dfail(HS_EBUDGET, "no step count up to 2^24 meets the budget");
+    // the SpME stopping rule of each probe, evaluated from the tables
+    auto ok = [&](long long r, bool *res) -> hs_status {
+        const double dt = std::fabs(t / (double)r);
+        double c = 1.0;
+        for (int k = 1; k <= max_iter; ++k) {
+            c = c * dt / k;
+            if (hs_status s = power(k)) return s;
+            if (c * mk[k] < tol) { *res = true; return HS_OK; }   // every kept term was within budget
+            if (uk[k] > (size_t)budget) { *res = false; return HS_OK; }
+        }
+        *res = true;
+        return HS_OK;
+    };
+    auto search = [&]() -> hs_status {
+        bool f = false;
+        long long lo = 1;
+        if (hs_status s = ok(lo, &f)) return s;
+        if (f) { *steps = 1; return HS_OK; }
+        long long u = 2;
+        for (;;) {
+            if (hs_status s = ok(u, &f)) return s;
+            if (f) break;
+            lo = u;
+            u *= 2;
+            if (u > (1ll << 24)) return dfail(HS_EBUDGET, "no step count up to 2^24 meets the budget");
+        }
+        while (u - lo > 1) {
+            const long long mid = (lo + u) / 2;
+            if (hs_status s = ok(mid, &f)) return s;
+            if (f) u = mid; else lo = mid;
+        }
+        *steps = (int)u;
+        return HS_OK;
+    };
+    hs_status s = search();
+    release();
+    if (s == HS_OK) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return dhip(e, "hipStreamSynchronize");
     }
-    while (u - lo > 1) {
-        const long long mid = (lo + u) / 2;
-        if (hs_status s = ok(mid, &f)) return s;
-        if (f) u = mid; else lo = mid;
-    }
-    *steps = (int)u;
-    return HS_OK;
+    return s;
 }
 
 hs_status hs_dia_to_c64(hs_dia A, void *stream, hs_dia *out) {

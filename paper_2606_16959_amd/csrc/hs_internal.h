@@ -48,6 +48,7 @@ struct Plan {
     int order = 1;                  // product formula: 1, 2 (symmetric) or 4 (Suzuki)
     std::vector<Factor> factors;    // distinct stored factors
     std::vector<int> seq;           // factor indices applied in one step, in order
+    int joint = -1;                 // factor that joins the last and first of consecutive steps
 };
 
 // Host-side planning (no device calls).  Returns HS_OK or an error with msg.

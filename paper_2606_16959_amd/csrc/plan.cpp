@@ -275,8 +275,16 @@ hs_status make_plan(int n, int n_terms, const char *const *strings, const double
             s2(p * P.dt);
             s2(p * P.dt);
         }
-        std::map<std::pair<int, double>, int> made;
+        // Neighbours with the same generator combine, exp(-i a G) exp(-i b G) =
+        // exp(-i (a + b) G): S4's junctions F_1(p dt/2) F_1(p dt/2) and the
+        // like.  Sums are taken left to right.
+        std::vector<std::pair<int, double>> merged;
         for (auto &e : seq) {
+            if (!merged.empty() && merged.back().first == e.first) merged.back().second += e.second;
+            else merged.push_back(e);
+        }
+        std::map<std::pair<int, double>, int> made;
+        auto stored = [&](const std::pair<int, double> &e) {
             auto it = made.find(e);
             if (it == made.end()) {
                 const bool is_diag = !P.diag.empty() && e.first == 0;
@@ -284,8 +292,13 @@ hs_status make_plan(int n, int n_terms, const char *const *strings, const double
                 P.factors.push_back(is_diag ? diag_factor(e.second) : group_factor(groups[g], e.second, false));
                 it = made.emplace(e, (int)P.factors.size() - 1).first;
             }
-            P.seq.push_back(it->second);
-        }
+            return it->second;
+        };
+        for (auto &e : merged) P.seq.push_back(stored(e));
+        // A symmetric step starts and ends with F_1, so consecutive steps meet
+        // in F_1(last h) F_1(first h): stored once as the joint factor.
+        if (merged.size() > 1 && merged.front().first == merged.back().first)
+            P.joint = stored({merged.front().first, merged.back().second + merged.front().second});
     }
     for (auto &f : P.factors) {
         if (f.xmask_union) {

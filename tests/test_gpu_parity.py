@@ -345,10 +345,13 @@ def test_higher_order_products_match_oracle(order):
     terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
     part = ofac.first_fit(terms, 8, 0.1)
     f = hs.build_factors(H.strings, H.coeffs, 8, 1.0, 10, 8, dtype="c128", order=order)
-    p = _to_dev(torch, ws.zero_state(8)[None], np.complex128)
-    hs.evolve(f, p, 10)
-    ref = oev.evolve(terms, part, ws.zero_state(8), 8, 0.1, 10, order=order)
-    assert np.abs(p.cpu().numpy()[0] - ref).max() <= 1e-12
+    assert f.describe()["joint"] >= 0
+    # one step (the plain sequence), two (first and last parts), ten (middle parts too)
+    for r in (1, 2, 10):
+        p = _to_dev(torch, ws.zero_state(8)[None], np.complex128)
+        hs.evolve(f, p, r)
+        ref = oev.evolve(terms, part, ws.zero_state(8), 8, 0.1, r, order=order)
+        assert np.abs(p.cpu().numpy()[0] - ref).max() <= 1e-12, r
     # fused and unfused launches agree bit for bit
     q = _to_dev(torch, ws.zero_state(8)[None], np.complex128)
     hs.evolve(f, q, 10, fuse=False)

@@ -97,11 +97,16 @@ def test_spme_matches_oracle(which, dt):
     H.close()
 
 
-@pytest.mark.parametrize("n,budget,t", [(5, 11, 1.0), (5, 40, 1.0), (6, 13, 0.5), (4, 9, 2.0)])
-def test_step_search_matches_oracle(n, budget, t):
+@pytest.mark.parametrize("which,n,budget,t", [("tfim", 5, 11, 1.0), ("tfim", 5, 40, 1.0), ("tfim", 6, 13, 0.5),
+                                               ("tfim", 4, 9, 2.0), ("tfim", 8, 200, 0.5), ("heis", 9, 60, 1.0),
+                                               ("heis", 8, 400, 0.3)])
+def test_step_search_matches_oracle(which, n, budget, t):
+    """The search shares powers of H across probes; the oracle recomputes
+    each probe's Taylor chain (Alg. 2) from scratch.  The last two cases keep
+    two and four terms, so powers up to H^4 are stored."""
     hd, torch = _dia()
-    Hw = wh.tfim_1d(n, 1.0, 1.0)
-    note(f"estimate_timesteps tfim n={n} budget={budget}")
+    Hw = wh.tfim_1d(n, 1.0, 1.0) if which == "tfim" else wh.heisenberg_1d(n, 1.0, fields=np.linspace(-1, 1, n))
+    note(f"estimate_timesteps {which} n={n} budget={budget}")
     H = hd.from_pauli(Hw.strings, Hw.coeffs, n)
     r = hd.estimate_timesteps(H, t, budget)
     assert r == ospme.estimate_timesteps(ospme.hamiltonian_from_strings(Hw.strings, Hw.coeffs, n), t, budget)

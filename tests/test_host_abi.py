@@ -151,7 +151,7 @@ def test_higher_order_plan_matches_oracle_sequence(hs, cfg, order):
     f = hs.plan(H.strings, H.coeffs, H.n, run["t"], run["steps"], run["budget"], order=order)
     desc = f.describe()
     terms, part = _oracle_partition(H, run["budget"], run["t"], run["steps"])
-    seq = oev.product_sequence(part, dt, order)
+    seq = oev.merge_adjacent(oev.product_sequence(part, dt, order))
     assert len(desc["sequence"]) == len(seq)
     for k, (g, h) in zip(desc["sequence"], seq):
         fac = desc["factors"][k]
@@ -160,7 +160,32 @@ def test_higher_order_plan_matches_oracle_sequence(hs, cfg, order):
         assert fac["terms"] == ([] if g < 0 else part.groups[g])
         grp = [] if g < 0 else part.groups[g]
         assert fac["offsets"] == ofac.factor_offsets(terms, (g < 0, grp), h)
+    # where steps meet, the last and first factor join into one stored factor
+    g0, hj = seq[0][0], seq[-1][1] + seq[0][1]
+    assert seq[-1][0] == g0 and desc["joint"] >= 0
+    jf = desc["factors"][desc["joint"]]
+    assert jf["dt"] == hj and jf["terms"] == ([] if g0 < 0 else part.groups[g0])
+    # the parts of an evolution of r steps spell out the merged product S(dt)^r
+    for r in (2, 3, 5):
+        got = f.part_sequence(1, desc) + f.part_sequence(2, desc) * (r - 2) + f.part_sequence(3, desc)
+        want = oev.merge_adjacent(oev.product_sequence(part, dt, order) * r)
+        assert [(desc["factors"][k]["terms"], desc["factors"][k]["dt"]) for k in got] == \
+            [([] if g < 0 else part.groups[g], h) for g, h in want]
     # each distinct (factor, step) pair is stored once
-    pairs = {(g, h) for g, h in seq}
+    pairs = {(g, h) for g, h in seq} | {(g0, hj)}
     assert len(desc["factors"]) == len(pairs)
     f.close()
+
+
+def test_first_order_and_single_factor_steps_have_no_joint(hs):
+    H = config_hamiltonian(1)
+    f = hs.plan(H.strings, H.coeffs, H.n, 1.0, 10, 8)
+    assert f.describe()["joint"] == -1
+    f.close()
+    # a diagonal Hamiltonian is one factor: S2 and S4 collapse to it
+    for order in (2, 4):
+        f = hs.plan(["ZZI", "IZZ"], [1.0, 0.5], 3, 1.0, 10, 4, order=order)
+        d = f.describe()
+        assert d["joint"] == -1 and len(d["sequence"]) == 1
+        assert abs(d["factors"][0]["dt"] - 0.1) < 1e-15
+        f.close()

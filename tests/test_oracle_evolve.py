@@ -257,6 +257,34 @@ def test_product_sequences_are_symmetric():
 
 
 @pytest.mark.parametrize("order", [2, 4])
+def test_merged_neighbours_give_the_same_product(order):
+    """Combining same-generator neighbours, within a step and where steps
+    meet, leaves S(dt)^r unchanged (exp(aG) exp(bG) = exp((a+b)G))."""
+    H = _heis(4)
+    dt, r = 0.23, 3
+    terms, part = _setup(H, 16, dt)
+    one = oev.product_sequence(part, dt, order)
+    whole = oev.merge_adjacent(one * r)
+    L = len(part.groups) + (1 if part.diag else 0)
+    assert L >= 2
+    # S4 meets itself four times inside a step; every step boundary joins once
+    inner = 4 if order == 4 else 0
+    assert len(oev.merge_adjacent(one)) == len(one) - inner
+    assert len(whole) == r * (len(one) - inner) - (r - 1)
+    assert all(a[0] != b[0] for a, b in zip(whole, whole[1:]))
+    # the total time of every factor is preserved
+    for g in [-1] + list(range(len(part.groups))):
+        assert abs(sum(h for q, h in whole if q == g) - r * dt) < 1e-14
+    psi0 = _rand_state(4, 5)
+    ref = _expm_sequence(terms, part, 4, dt, r, psi0, order)
+    U = np.eye(16, dtype=np.complex128)
+    for g, h in whole:
+        idx = part.diag if g < 0 else part.groups[g]
+        U = sl.expm(-1j * h * pauli.dense_hamiltonian([terms[k] for k in idx], 4)) @ U
+    assert np.abs(U @ psi0 - ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("order", [2, 4])
 def test_higher_order_equals_expm_products_and_numpy_twin(oracle_lib, order):
     H = _heis(5)
     dt, r = 0.17, 3
