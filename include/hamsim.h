@@ -243,16 +243,21 @@ hs_status hs_dia_copy_diagonal(hs_dia A, int j, long long start, long long count
 hs_status hs_dia_spgemm(hs_dia A, hs_dia B, void *stream, hs_dia *C);
 /* largest entry modulus (FP64); syncs */
 hs_status hs_dia_maxabs(hs_dia A, void *stream, double *out);
-/* Alg. 2: X = -i H dt; U = T = I; for k = 1..max_iter: T <- T X / k; stop
- * when max |T_ij| < tol (T not added), else U += T.  A diagonal H takes the
- * exact elementwise exponential.  *n_terms = the number of Taylor terms added
- * after I (0 for diagonal H).  No scaling-and-squaring.  Each term's norm is
- * computed before the term is stored, so the dropped term takes no memory.
- * Syncs. */
-hs_status hs_spme(hs_dia H, double dt, double tol, int max_iter, void *stream, hs_dia *U,
-                  int *n_terms);
-/* Smallest r such that hs_spme(H, t / r, tol, max_iter) has at most `budget`
- * diagonals (structural count): r = 1 for diagonal H; else r = 1 if it
+/* Alg. 2 in its scaling-and-squaring form (SpME subsection):
+ * X = -i H dt / 2^s; U = T = I; for k = 1..max_iter: T <- T X / k; stop when
+ * max |T_ij| < tol (T not added), else U += T; then s times U <- U U (SpGEMM).
+ * squarings: s, or -1 for the smallest s >= 0 with |dt| nu / 2^s <= 1/2,
+ * where nu = the sum over H's diagonals (ascending offset) of their largest
+ * entry modulus (>= ||H||_1, ||H||_inf, ||H||_2); at most 60.  A diagonal H
+ * takes the exact elementwise exponential.  *n_terms = the number of Taylor
+ * terms added after I (0 for diagonal H).  Each term's norm is computed
+ * before the term is stored, so the dropped term takes no memory.  H must
+ * be complex128.  Syncs. */
+hs_status hs_spme(hs_dia H, double dt, double tol, int max_iter, int squarings, void *stream,
+                  hs_dia *U, int *n_terms);
+/* Smallest r such that hs_spme(H, t / r, tol, max_iter, -1) has at most
+ * `budget` diagonals (structural count, after squaring: each squaring maps
+ * the offset set S to S + S): r = 1 for diagonal H; else r = 1 if it
  * meets the budget, otherwise doubling u = 2, 4, ... until it does, then
  * bisection between the last failing and the first passing value.  A probe
  * stops as soon as a Taylor term above the tolerance would push the count

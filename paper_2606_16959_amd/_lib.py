@@ -51,7 +51,7 @@ _SIG = {
     "hs_dia_copy_diagonal": (_I, [_P, _I, _LL, _LL, _P, _P]),
     "hs_dia_spgemm": (_I, [_P, _P, _P, ctypes.POINTER(_P)]),
     "hs_dia_maxabs": (_I, [_P, _P, ctypes.POINTER(_D)]),
-    "hs_spme": (_I, [_P, _D, _D, _I, _P, ctypes.POINTER(_P), ctypes.POINTER(_I)]),
+    "hs_spme": (_I, [_P, _D, _D, _I, _I, _P, ctypes.POINTER(_P), ctypes.POINTER(_I)]),
     "hs_estimate_timesteps": (_I, [_P, _D, _I, _D, _I, _P, ctypes.POINTER(_I)]),
     "hs_dia_to_c64": (_I, [_P, _P, ctypes.POINTER(_P)]),
     "hs_dia_evolve": (_I, [_P, _P, _I, _I, _P]),

@@ -239,12 +239,48 @@ hs_status dia_sum(hs_dia U, hs_dia T, hipStream_t st, hs_dia *out) {
     return HS_OK;
 }
 
-// Alg. 2.  cap > 0: stop as soon as the propagator would exceed cap diagonals
-// with a term above the tolerance (*exceeded = true, *out = null).
-hs_status spme_impl(hs_dia H, double dt, double tol, int max_iter, int cap, hipStream_t st,
-                    hs_dia *out, int *K, bool *exceeded) {
+// Largest entry modulus of each diagonal of A (FP64, A complex128).
+hs_status diag_maxima(hs_dia A, hipStream_t st, std::vector<double> &out) {
+    if (hs_status s = dia_tables(A)) return s;
+    const int gx = hs::dia_grid_x(A->N);
+    const size_t nd = A->offs.size();
+    Temps tmp(st);
+    std::vector<double> blocks((size_t)gx * nd, 0.0);
+    double *bmax = nullptr;
+    DHIP(tmp.up(blocks, &bmax), "maxabs table");
+    int le = hs::launch_dia_maxabs(reinterpret_cast<const double *const *>(A->d_ptrs), A->d_offs, A->N,
+                                   (int)nd, gx, bmax, st);
+    if (le) return dhip((hipError_t)le, "maxabs kernel");
+    DHIP(hipMemcpyAsync(blocks.data(), bmax, blocks.size() * sizeof(double), hipMemcpyDeviceToHost, st),
+         "download");
+    DHIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    out.assign(nd, 0.0);
+    for (size_t j = 0; j < nd; ++j)
+        for (int b = 0; b < gx; ++b) out[j] = std::max(out[j], blocks[j * gx + b]);
+    return HS_OK;
+}
+
+// Scaling rule for the Taylor series: the smallest s >= 0 with
+// |dt| nu / 2^s <= 1/2, nu = sum over H's diagonals (ascending offset) of
+// their largest entry modulus, which bounds ||H||_1, ||H||_inf and ||H||_2.
+hs_status auto_squarings(hs_dia H, double dt, hipStream_t st, int *s_out) {
+    std::vector<double> mx;
+    if (hs_status s = diag_maxima(H, st, mx)) return s;
+    double nu = 0.0;
+    for (double v : mx) nu += v;
+    const double x = std::fabs(dt) * nu;
+    int s = 0;
+    while (x > 0.5 * std::ldexp(1.0, s)) ++s;
+    *s_out = s;
+    return HS_OK;
+}
+
+// Alg. 2 with scaling and squaring: the Taylor series of X = -i H dt / 2^s,
+// then s squarings U <- U U by SpGEMM.  squarings < 0 selects s by the rule
+// above.
+hs_status spme_impl(hs_dia H, double dt, double tol, int max_iter, int squarings, hipStream_t st,
+                    hs_dia *out, int *K) {
     *out = nullptr;
-    *exceeded = false;
     *K = 0;
     if (H->dtype != HS_C128) return dfail(HS_EINVAL, "the exponential needs a complex128 operator");
     if (H->offs.size() == 1 && H->offs[0] == 0) {      // diagonal: exact, elementwise
@@ -256,17 +292,15 @@ hs_status spme_impl(hs_dia H, double dt, double tol, int max_iter, int cap, hipS
         *out = U;
         return HS_OK;
     }
+    int sq = squarings;
+    if (sq < 0)
+        if (hs_status s = auto_squarings(H, dt, st, &sq)) return s;
+    const double h = std::ldexp(dt, -sq);               // dt / 2^s, exact
     hs_dia U = nullptr, T = nullptr;
     if (hs_status s = identity(H->N, st, &U)) return s;
     if (hs_status s = identity(H->N, st, &T)) { delete U; return s; }
     for (int k = 1; k <= max_iter; ++k) {
-        // structural offsets of T_k and of U + T_k
-        std::set<int64_t> toffs, un(U->offs.begin(), U->offs.end());
-        for (int64_t a : T->offs)
-            for (int64_t b : H->offs)
-                if (a + b > -H->N && a + b < H->N) toffs.insert(a + b);
-        un.insert(toffs.begin(), toffs.end());
-        const double sre = 0.0, sim = -dt / k;        // T_k = T_{k-1} (-i dt H) / k
+        const double sre = 0.0, sim = -h / k;          // T_k = T_{k-1} (-i h H) / k
         // The stopping test needs only T_k's largest entry: a first pass
         // computes it without storing T_k, so the final (dropped) term, the
         // largest one, never occupies memory.  Kept terms are computed again
@@ -275,12 +309,6 @@ hs_status spme_impl(hs_dia H, double dt, double tol, int max_iter, int cap, hipS
         hs_status s = spgemm(T, H, sre, sim, false, st, nullptr, &norm);
         if (s) { delete U; delete T; return s; }
         if (norm < tol) break;
-        if (cap > 0 && (int)un.size() > cap) {      // kept and over the budget
-            *exceeded = true;
-            delete U;
-            delete T;
-            return HS_OK;
-        }
         hs_dia Tn = nullptr;
         s = spgemm(T, H, sre, sim, true, st, &Tn, &norm);
         delete T;
@@ -294,6 +322,14 @@ hs_status spme_impl(hs_dia H, double dt, double tol, int max_iter, int cap, hipS
         *K = k;
     }
     delete T;
+    for (int j = 0; j < sq; ++j) {
+        hs_dia Un = nullptr;
+        double unused = 0.0;
+        hs_status s = spgemm(U, U, 1.0, 0.0, true, st, &Un, &unused);
+        delete U;
+        if (s) return s;
+        U = Un;
+    }
     DHIP(hipStreamSynchronize(st), "hipStreamSynchronize");
     *out = U;
     return HS_OK;
@@ -487,12 +523,13 @@ hs_status hs_dia_maxabs(hs_dia A, void *stream, double *out) {
     return max_of_blocks(bmax, zeros.size(), st, out);
 }
 
-hs_status hs_spme(hs_dia H, double dt, double tol, int max_iter, void *stream, hs_dia *U, int *n_terms) {
+hs_status hs_spme(hs_dia H, double dt, double tol, int max_iter, int squarings, void *stream, hs_dia *U,
+                  int *n_terms) {
     if (!H || !U) return dfail(HS_EINVAL, "null argument");
     if (!(tol > 0.0) || max_iter < 1 || !std::isfinite(dt)) return dfail(HS_EINVAL, "bad tolerance or iterations");
+    if (squarings > 60) return dfail(HS_EINVAL, "squarings must be <= 60");
     int K = 0;
-    bool exceeded = false;
-    hs_status s = spme_impl(H, dt, tol, max_iter, 0, S(stream), U, &K, &exceeded);
+    hs_status s = spme_impl(H, dt, tol, max_iter, squarings, S(stream), U, &K);
     if (n_terms) *n_terms = K;
     return s;
 }
@@ -516,6 +553,7 @@ hs_status hs_estimate_timesteps(hs_dia H, double t, int budget, double tol, int 
     std::vector<double> mk{0.0};                    // mk[k] = max |H^k|
     std::vector<size_t> uk{1};                      // uk[k] = |offsets of H^0 .. H^k|
     std::set<int64_t> un{0};
+    std::vector<std::set<int64_t>> upto{un};        // upto[k] = offsets of H^0 .. H^k
     std::vector<int64_t> poffs{0};                  // structural offsets of H^(mk.size() - 1)
     hs_dia P = H;                                   // H^p, owned when p >= 2
     int p = 1;
@@ -548,20 +586,43 @@ hs_status hs_estimate_timesteps(hs_dia H, double t, int budget, double tol, int 
             un.insert(nx.begin(), nx.end());
             mk.push_back(m);
             uk.push_back(un.size());
+            upto.push_back(un);
         }
         return HS_OK;
     };
-    // the SpME stopping rule of each probe, evaluated from the tables
+    // scaling rule of hs_spme: |dt| nu / 2^s <= 1/2
+    std::vector<double> dmax;
+    if (hs_status s = diag_maxima(H, st, dmax)) return s;
+    double nu = 0.0;
+    for (double v : dmax) nu += v;
+    // the SpME stopping rule of each probe, evaluated from the tables, then
+    // the offsets of s squarings (S <- S + S; the set only grows, as 0 is in S)
     auto ok = [&](long long r, bool *res) -> hs_status {
-        const double dt = std::fabs(t / (double)r);
+        const double dt = t / (double)r;
+        int sq = 0;
+        while (std::fabs(dt) * nu > 0.5 * std::ldexp(1.0, sq)) ++sq;
+        const double h = std::fabs(std::ldexp(dt, -sq));
         double c = 1.0;
+        int K = max_iter;
         for (int k = 1; k <= max_iter; ++k) {
-            c = c * dt / k;
+            c = c * h / k;
             if (hs_status s = power(k)) return s;
-            if (c * mk[k] < tol) { *res = true; return HS_OK; }   // every kept term was within budget
+            if (c * mk[k] < tol) { K = k - 1; break; }           // every kept term was within budget
             if (uk[k] > (size_t)budget) { *res = false; return HS_OK; }
         }
         *res = true;
+        if (sq == 0) return HS_OK;
+        std::set<int64_t> cur = upto[K];
+        for (int j = 0; j < sq && *res; ++j) {
+            std::set<int64_t> nx;
+            for (int64_t a : cur) {
+                for (int64_t b : cur)
+                    if (a + b > -H->N && a + b < H->N) nx.insert(a + b);
+                if (nx.size() > (size_t)budget) break;
+            }
+            if (nx.size() > (size_t)budget) *res = false;
+            cur.swap(nx);
+        }
         return HS_OK;
     };
     auto search = [&]() -> hs_status {

@@ -96,12 +96,14 @@ def spgemm(A: DiaOperator, B: DiaOperator, stream=None) -> DiaOperator:
     return DiaOperator(h)
 
 
-def spme(H: DiaOperator, dt: float, tol: float = 1e-6, max_iter: int = 30, stream=None):
-    """(U, n_terms) with U ~ exp(-i H dt) by the truncated Taylor series."""
+def spme(H: DiaOperator, dt: float, tol: float = 1e-6, max_iter: int = 30, squarings: int = -1,
+         stream=None):
+    """(U, n_terms) with U ~ exp(-i H dt) by the truncated Taylor series with
+    scaling and squaring (`squarings` -1: the library's rule; 0: none)."""
     h = ctypes.c_void_p()
     k = ctypes.c_int()
-    _lib.check(_lib.load().hs_spme(H.handle, float(dt), float(tol), int(max_iter), _stream_ptr(stream),
-                                   ctypes.byref(h), ctypes.byref(k)))
+    _lib.check(_lib.load().hs_spme(H.handle, float(dt), float(tol), int(max_iter), int(squarings),
+                                   _stream_ptr(stream), ctypes.byref(h), ctypes.byref(k)))
     return DiaOperator(h), k.value
 
 

@@ -72,8 +72,10 @@ def test_spgemm_matches_dense_product(N, kind):
         X.close()
 
 
-@pytest.mark.parametrize("which,dt", [("tfim", 0.02), ("tfim", 0.3), ("heis", 0.05), ("tsp", 0.5)])
-def test_spme_matches_oracle(which, dt):
+@pytest.mark.parametrize("squarings", [-1, 0, 2])
+@pytest.mark.parametrize("which,dt", [("tfim", 0.02), ("tfim", 0.3), ("heis", 0.05), ("tsp", 0.5),
+                                      ("heis", 0.8)])
+def test_spme_matches_oracle(which, dt, squarings):
     hd, torch = _dia()
     if which == "tfim":
         Hw = wh.tfim_1d(8, 1.0, 1.0)
@@ -84,10 +86,13 @@ def test_spme_matches_oracle(which, dt):
         d = rng.uniform(1, 10, (3, 3))
         d = np.triu(d, 1) + np.triu(d, 1).T
         Hw = wh.tsp_onehot(d, 20.0)            # 9 qubits, diagonal
-    note(f"spme {which} dt={dt}")
+    if which == "heis" and dt == 0.8 and squarings == 0:
+        pytest.skip("unscaled series at |dt| nu ~ 16: terms near 1e6 cancel, so an absolute bar does not apply")
+    note(f"spme {which} dt={dt} squarings={squarings}")
     H = hd.from_pauli(Hw.strings, Hw.coeffs, Hw.n)
-    U, K = hd.spme(H, dt)
-    Uref, Kref, offs = ospme.spme(ospme.hamiltonian_from_strings(Hw.strings, Hw.coeffs, Hw.n), dt)
+    U, K = hd.spme(H, dt, squarings=squarings)
+    Uref, Kref, offs = ospme.spme(ospme.hamiltonian_from_strings(Hw.strings, Hw.coeffs, Hw.n), dt,
+                                  n_squarings=None if squarings < 0 else squarings)
     assert K == Kref
     assert U.offsets == offs
     N = 1 << Hw.n
