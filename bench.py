@@ -392,6 +392,55 @@ def higher_order_leg(torch, steps=10, warmup=3):
     return out
 
 
+def taylor_leg(torch, cases=None, timed_steps=3):
+    """The Taylor expansion fused into the state update (complex64): H's
+    diagonals once, r = smallest step count with |dt| nu(H) <= 1, K from the
+    1e-6 tolerance, each step K Horner stages (one DIA SpMV of H with the
+    update in its epilogue).  Algorithmic bytes per stage: every stored
+    diagonal of H once, plus the state read (partners), the step's input read
+    (epilogue) and the output written."""
+    import paper_2606_16959_amd.dia as hd
+    from workloads import config_hamiltonian, hamiltonians as wh, states as ws
+    cases = cases or [("tfim1d_n24_h1_t1", lambda: wh.tfim_1d(24, 1.0, 1.0)),
+                      ("tfim2d_5x5_plus1_n26_t1", lambda: config_hamiltonian(3))]
+    out = []
+    for name, make in cases:
+        Hw = make()
+        n, N = Hw.n, 1 << Hw.n
+        t0 = time.perf_counter()
+        H = hd.from_pauli(Hw.strings, Hw.coeffs, n)
+        nu = hd.norm_bound(H)
+        r = hd.taylor_steps(H, 1.0)
+        K = hd.taylor_terms(H, 1.0 / r)
+        H64 = H.to_c64()
+        offs = H64.offsets
+        H.close()
+        setup_s = time.perf_counter() - t0
+        psi = torch.from_numpy(ws.random_phase_state(n, 7, np.complex64)).cuda()
+        hd.taylor_evolve(H64, psi, 1.0 / r, K, 1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        hd.taylor_evolve(H64, psi, 1.0 / r, K, timed_steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / timed_steps
+        stage_bytes = sum((N - abs(d)) * 8 for d in offs) + 3 * N * 8
+        row = {"workload": name, "n": n, "dtype": "c64", "nu": round(nu, 4), "steps_for_t1": r,
+               "taylor_terms": K, "h_diagonals": len(offs), "setup_s": round(setup_s, 3),
+               "ms_per_step": round(ms, 4), "ms_per_stage": round(ms / K, 4),
+               "gb_per_stage": round(stage_bytes / 1e9, 3),
+               "gbs": round(stage_bytes * K / ms / 1e6, 1),
+               "full_run_s_estimate": round(ms * r / 1e3, 3)}
+        row["frac_of_peak"] = round(row["gbs"] / HBM_PEAK_GBS, 4)
+        out.append(row)
+        log(f"taylor {name}: r={r} K={K} {ms:.3f} ms/step {row['gbs']} GB/s; t=1 in {row['full_run_s_estimate']} s")
+        H64.close()
+        del psi
+        torch.cuda.empty_cache()
+    return out
+
+
 def write_serve_summary(stats, command, fname):
     md = ["# Served stream: mixed TFIM / Heisenberg / MaxCut / TSP jobs, n in [10, 24], complex64", "",
           f"Command (repository root, GPU box): `{command}`", "",
@@ -469,6 +518,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-oracle-nmax", type=int, default=16)
     ap.add_argument("--serve-only", action="store_true", help="only the served stream")
+    ap.add_argument("--leg", choices=["taylor", "higher_order", "single_propagator", "other_configs"],
+                    help="run one secondary leg alone and print its JSON (for profiling)")
     ap.add_argument("--no-other-configs", action="store_true")
     ap.add_argument("--serve-sweep", default="", help="comma-separated arrival rates (jobs/s)")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
@@ -496,6 +547,11 @@ def main():
     torch.cuda.set_device(0)
     if args.sweep:
         sweep(torch, args.steps, args.warmup)
+        return
+    if args.leg:
+        legs = {"taylor": taylor_leg, "higher_order": higher_order_leg,
+                "single_propagator": single_propagator_leg, "other_configs": other_configs}
+        print(json.dumps({"leg": args.leg, "result": legs[args.leg](torch)}), flush=True)
         return
     if args.serve_only:
         st = serve_leg(torch, args.serve_jobs, args.serve_rate, args.serve_slots, args.serve_oracle_nmax)
@@ -583,6 +639,7 @@ def main():
         torch.cuda.empty_cache()
         others = other_configs(torch)
         others.append({"higher_order": higher_order_leg(torch)})
+        others.append({"taylor_fused": taylor_leg(torch)})
         others.append({"single_propagator": single_propagator_leg(torch)})
     serve = None
     if args.serve_jobs > 0:

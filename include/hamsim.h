@@ -273,6 +273,32 @@ hs_status hs_dia_to_c64(hs_dia A, void *stream, hs_dia *out);
  * by repeated DIA SpMV (out of place with library scratch, result written
  * back to psi).  Synchronises `stream`. */
 hs_status hs_dia_evolve(hs_dia U, void *psi, int batch, int steps, void *stream);
+/* nu(A) = sum over A's stored diagonals (ascending offset) of each one's
+ * largest entry modulus; bounds ||A||_1, ||A||_inf and ||A||_2.  Syncs. */
+hs_status hs_dia_norm_bound(hs_dia A, void *stream, double *nu);
+
+/*
+ * The Taylor expansion of exp(-i H dt) fused into the state update (future-
+ * work section: no propagator is formed).  One step applies
+ *     p_K(X) x = sum_{k=0..K} X^k x / k!,   X = -i dt H,
+ * by Horner's rule, K stages w <- x + (-i dt / j) H w for j = K .. 1 from
+ * w = x, each stage one DIA SpMV of H (Alg. 1) with the update fused into
+ * its epilogue.  H is read once per stage; U is never built, so the memory
+ * and traffic of the propagator's diagonals (Alg. 2, Section 3.2) vanish.
+ */
+/* Smallest K >= 1 (at most max_terms <= 64) with (|dt| nu(H))^(K+1) / (K+1)!
+ * < tol: the first dropped term of the series then has 2-norm below tol.
+ * HS_EBUDGET when max_terms is not enough.  Syncs. */
+hs_status hs_taylor_terms(hs_dia H, double dt, double tol, int max_terms, void *stream, int *K);
+/* Smallest r >= 1 with |t / r| nu(H) <= theta (theta > 0), the step count
+ * that keeps X small enough for a short series; HS_EBUDGET above 2^30.
+ * Syncs. */
+hs_status hs_taylor_steps(hs_dia H, double t, double theta, void *stream, int *steps);
+/* psi <- p_K(-i dt H)^steps psi for `batch` device states ([batch][N], of
+ * H's dtype, 16-byte aligned), 1 <= K <= 64.  In place; library scratch of
+ * two states per chunk of HS_MAX_BATCH (one for K = 1), stream-ordered.
+ * Synchronises `stream`. */
+hs_status hs_taylor_evolve(hs_dia H, void *psi, int batch, double dt, int K, int steps, void *stream);
 hs_status hs_dia_free(hs_dia A);
 
 /* Message for the calling thread's last non-OK status ("" if none). */

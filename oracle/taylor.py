@@ -72,3 +72,30 @@ def taylor_evolve(H, psi: np.ndarray, dt: float, K: int, steps: int) -> np.ndarr
 def remainder_bound(x: float, K: int) -> float:
     """sum_{k > K} x^k / k!  (>= ||exp(X) - p_K(X)||_2 when ||X||_2 <= x)."""
     return sum(x ** k / math.factorial(k) for k in range(K + 1, K + 80))
+
+
+def _apply_rows(terms, rows: np.ndarray, values_at) -> np.ndarray:
+    """(H v)[rows] from the Pauli action H[y, y^m] += c i^ny (-1)^{popcount((y^m) & z)},
+    where values_at(idx) returns v[idx]."""
+    from .pauli import popcount_array
+    out = np.zeros(len(rows), dtype=np.complex128)
+    for t in terms:
+        col = rows ^ np.int64(t.xmask)
+        sign = 1.0 - 2.0 * (popcount_array(col & np.int64(t.zmask)) & 1)
+        out += t.coeff * (1j) ** t.ny * sign * values_at(col)
+    return out
+
+
+def step_rows(terms, x: np.ndarray, rows, dt: float, K: int) -> np.ndarray:
+    """Entries `rows` of one step sum_{k<=K} (-i dt H)^k x / k! for a state
+    too large to multiply whole: (X^k x / k!)[idx] is formed from
+    (X^(k-1) x / (k-1)!) at the rows that idx couples to, recursively (cost
+    grows as (#terms)^K per sampled row)."""
+    rows = np.asarray(rows, dtype=np.int64)
+
+    def v(k, idx):
+        if k == 0:
+            return np.asarray(x[idx], dtype=np.complex128)
+        return (-1j * dt / k) * _apply_rows(terms, idx, lambda c: v(k - 1, c))
+
+    return sum(v(k, rows) for k in range(K + 1))

@@ -52,6 +52,10 @@ _SIG = {
     "hs_dia_spgemm": (_I, [_P, _P, _P, ctypes.POINTER(_P)]),
     "hs_dia_maxabs": (_I, [_P, _P, ctypes.POINTER(_D)]),
     "hs_spme": (_I, [_P, _D, _D, _I, _I, _P, ctypes.POINTER(_P), ctypes.POINTER(_I)]),
+    "hs_dia_norm_bound": (_I, [_P, _P, ctypes.POINTER(_D)]),
+    "hs_taylor_terms": (_I, [_P, _D, _D, _I, _P, ctypes.POINTER(_I)]),
+    "hs_taylor_steps": (_I, [_P, _D, _D, _P, ctypes.POINTER(_I)]),
+    "hs_taylor_evolve": (_I, [_P, _P, _I, _D, _I, _I, _P]),
     "hs_estimate_timesteps": (_I, [_P, _D, _I, _D, _I, _P, ctypes.POINTER(_I)]),
     "hs_dia_to_c64": (_I, [_P, _P, ctypes.POINTER(_P)]),
     "hs_dia_evolve": (_I, [_P, _P, _I, _I, _P]),

@@ -721,6 +721,109 @@ hs_status hs_dia_evolve(hs_dia U, void *psi, int batch, int steps, void *stream)
     return HS_OK;
 }
 
+hs_status hs_dia_norm_bound(hs_dia A, void *stream, double *nu) {
+    if (!A || !nu) return dfail(HS_EINVAL, "null argument");
+    std::vector<double> mx;
+    if (hs_status s = diag_maxima(A, S(stream), mx)) return s;
+    double v = 0.0;
+    for (double m : mx) v += m;
+    *nu = v;
+    return HS_OK;
+}
+
+hs_status hs_taylor_terms(hs_dia H, double dt, double tol, int max_terms, void *stream, int *K) {
+    if (!H || !K || !(tol > 0.0) || max_terms < 1 || max_terms > 64 || !std::isfinite(dt))
+        return dfail(HS_EINVAL, "bad arguments");
+    double nu = 0.0;
+    if (hs_status s = hs_dia_norm_bound(H, stream, &nu)) return s;
+    const double x = std::fabs(dt) * nu;
+    double b = x;                                   // bound of term k: x^k / k!
+    for (int k = 1; k <= max_terms; ++k) {
+        b = b * x / (k + 1);
+        if (b < tol) {
+            *K = k;
+            return HS_OK;
+        }
+    }
+    return dfail(HS_EBUDGET, "|dt| nu(H) too large for max_terms Taylor terms; take more steps");
+}
+
+hs_status hs_taylor_steps(hs_dia H, double t, double theta, void *stream, int *steps) {
+    if (!H || !steps || !(theta > 0.0) || !std::isfinite(t)) return dfail(HS_EINVAL, "bad arguments");
+    double nu = 0.0;
+    if (hs_status s = hs_dia_norm_bound(H, stream, &nu)) return s;
+    const double r0 = std::ceil(std::fabs(t) * nu / theta);
+    if (!(r0 <= (double)(1 << 30))) return dfail(HS_EBUDGET, "more than 2^30 steps");
+    long long r = std::max(1ll, (long long)r0);
+    while (r > 1 && std::fabs(t / (double)(r - 1)) * nu <= theta) --r;   // rounding guards
+    while (std::fabs(t / (double)r) * nu > theta) ++r;
+    *steps = (int)r;
+    return HS_OK;
+}
+
+hs_status hs_taylor_evolve(hs_dia H, void *psi, int batch, double dt, int K, int steps, void *stream) {
+    if (!H || !psi || batch < 1 || steps < 0 || K < 1 || K > 64 || !std::isfinite(dt))
+        return dfail(HS_EINVAL, "bad arguments");
+    if (reinterpret_cast<uintptr_t>(psi) % 16) return dfail(HS_EINVAL, "state pointer must be 16-byte aligned");
+    if (steps == 0) return HS_OK;
+    hipStream_t st = S(stream);
+    const int64_t N = H->N;
+    const size_t sc = H->elem();
+    const bool c128 = H->dtype == HS_C128;
+    const int nd = (int)H->offs.size();
+    std::vector<long long> offs(H->offs.begin(), H->offs.end());
+    std::vector<const void *> ptrs(H->ptr.begin(), H->ptr.end());
+    Temps tmp(st);
+    const int chunk0 = std::min(HS_MAX_BATCH, batch);
+    void *buf[2] = {nullptr, nullptr};
+    for (int i = 0; i < (K == 1 ? 1 : 2); ++i) {
+        DHIP(hipMallocAsync(&buf[i], (size_t)chunk0 * N * sc, st), "hipMallocAsync(scratch)");
+        tmp.ptrs.push_back(buf[i]);
+    }
+    std::map<int, DiagDesc *> descs;
+    std::vector<std::vector<DiagDesc>> host_descs;
+    for (int c0 = 0; c0 < batch; c0 += HS_MAX_BATCH) {
+        const int chunk = std::min(HS_MAX_BATCH, batch - c0);
+        const Geo geo = generic_geometry(offs.data(), nd, N, H->dtype, chunk);
+        DiagDesc *dd = nullptr;
+        auto it = descs.find(chunk);
+        if (it == descs.end()) {
+            host_descs.emplace_back();
+            fill_descs(offs.data(), ptrs.data(), nd, N, geo, host_descs.back());
+            DHIP(tmp.up(host_descs.back(), &dd), "descriptors");
+            descs[chunk] = dd;
+        } else {
+            dd = it->second;
+        }
+        char *home = static_cast<char *>(psi) + (size_t)c0 * N * sc;
+        char *cur = home;
+        char *other = static_cast<char *>(buf[0]);
+        for (int s = 0; s < steps; ++s) {
+            // Horner: w <- x + (-i dt / j) H w for j = K .. 1, starting from w = x.
+            // The last stage writes over x itself (each row reads its own x
+            // entry only); with K = 1 the only stage reads x as w too, so it
+            // writes the other buffer and the roles swap.
+            const void *w = cur;
+            for (int j = K; j >= 1; --j) {
+                void *out = (K == 1) ? other : (j == 1 ? cur : buf[(K - j) & 1]);
+                TileArgs a = open_args(geo, dd, nd, w, out, N);
+                a.x0 = cur;
+                a.alpha_re = 0.0;
+                a.alpha_im = -dt / j;
+                int le = hs::launch_tile_horner(a, chunk, c128, st);
+                if (le) return dhip((hipError_t)le, "Horner tile kernel launch");
+                w = out;
+            }
+            if (K == 1) std::swap(cur, other);
+        }
+        if (cur != home) {
+            DHIP(hipMemcpyAsync(home, cur, (size_t)chunk * N * sc, hipMemcpyDeviceToDevice, st), "copy back");
+        }
+    }
+    DHIP(hipStreamSynchronize(st), "hipStreamSynchronize");   // temporaries are freed on return
+    return HS_OK;
+}
+
 hs_status hs_dia_free(hs_dia A) {
     delete A;
     return HS_OK;

@@ -80,6 +80,8 @@ struct TileArgs {
     const double *nrm2;      // per-state squared norms to divide out, or null
     int *viol;               // closure-violation flag (closed launches)
     int32_t swizzle;         // deal contiguous eighths of the tiles to the 8 XCDs
+    const void *x0;          // Horner launches: y = x0 + alpha (A x), x0 read at the row only
+    double alpha_re, alpha_im;
 };
 
 struct ConstructArgs {
@@ -102,6 +104,8 @@ int launch_phase_table(int64_t N, int nz, const uint64_t *zm, const double *cf, 
                        double *out, void *stream);
 int launch_construct(const ConstructArgs &a, int nd, int64_t max_len, bool c128, void *stream);
 int launch_tile(const TileArgs &a, int batch, bool c128, bool closed, void *stream);
+// open launch with the Horner epilogue y = x0 + alpha (A x); y may alias x0, not x
+int launch_tile_horner(const TileArgs &a, int batch, bool c128, void *stream);
 int launch_diag_elementwise(void *y, const void *x, const void *diag, int64_t N, int batch,
                             const double *nrm2, bool c128, void *stream);
 int launch_reduce(const void *A, int ta, const void *B, int tb, int batch, int64_t N,

@@ -167,6 +167,20 @@ __device__ __forceinline__ void ld2(const C2<double> *p, int i, C2<double> &a, C
     b = ld1(p, i + 1);
 }
 
+// State rows staged by open launches keep the default cache policy: other
+// tiles read them again as out-of-tile partners, and those reads should hit.
+__device__ __forceinline__ void ld2_cached(const C2<float> *p, int i, C2<float> &a, C2<float> &b) {
+    const f4v v = *((g_f4 *)(p) + (i >> 1));
+    a = C2<float>{v.x, v.y};
+    b = C2<float>{v.z, v.w};
+}
+__device__ __forceinline__ void ld2_cached(const C2<double> *p, int i, C2<double> &a, C2<double> &b) {
+    const d2v u = *((g_d2 *)(p) + i);
+    const d2v v = *((g_d2 *)(p) + i + 1);
+    a = C2<double>{u.x, u.y};
+    b = C2<double>{v.x, v.y};
+}
+
 template <typename R>
 __device__ __forceinline__ C2<R> cmask(C2<R> c, bool keep) {
     return keep ? c : C2<R>{(R)0, (R)0};
@@ -209,7 +223,9 @@ __device__ __forceinline__ void load_diag(C2<R> (&c)[P][2], const DiagDesc &dd, 
     }
 }
 
-template <typename R, int B, int RPT, bool CLOSED>
+// HORNER (open launches only): the output row is x0[r] + alpha * (A x)[r],
+// one Horner stage of a polynomial in A applied to a state.
+template <typename R, int B, int RPT, bool CLOSED, bool HORNER = false>
 __global__ __launch_bounds__(kTileThreads) void dia_tile_kernel(TileArgs a) {
     static_assert(RPT % 2 == 0, "rows come in pairs");
     constexpr int P = RPT / 2;
@@ -248,7 +264,10 @@ __global__ __launch_bounds__(kTileThreads) void dia_tile_kernel(TileArgs a) {
             const int i0 = 2 * tid + 2 * NT * p;
             const int r0 = i0 < T ? row_of(i0) : base;
 #pragma unroll
-            for (int b = 0; b < B; ++b) ld2(x + b * a.stride, r0, u[p][0][b], u[p][1][b]);
+            for (int b = 0; b < B; ++b) {
+                if (CLOSED) ld2(x + b * a.stride, r0, u[p][0][b], u[p][1][b]);
+                else ld2_cached(x + b * a.stride, r0, u[p][0][b], u[p][1][b]);
+            }
         }
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -346,6 +365,24 @@ __global__ __launch_bounds__(kTileThreads) void dia_tile_kernel(TileArgs a) {
         }
     }
 
+    if (HORNER) {
+        const C2<R> *x0 = reinterpret_cast<const C2<R> *>(a.x0);
+        const C2<R> al{(R)a.alpha_re, (R)a.alpha_im};
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+            const int r0 = i0 < T ? row_of(i0) : base;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                C2<R> v0, v1;
+                ld2(x0 + b * a.stride, r0, v0, v1);
+                cfma(v0, al, acc[p][0][b]);
+                cfma(v1, al, acc[p][1][b]);
+                acc[p][0][b] = v0;
+                acc[p][1][b] = v1;
+            }
+        }
+    }
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const int i0 = 2 * tid + 2 * NT * p;
@@ -480,36 +517,47 @@ int launch_construct(const ConstructArgs &a, int nd, int64_t max_len, bool c128,
     return (int)hipGetLastError();
 }
 
+enum TileMode { kOpen = 0, kClosed = 1, kHorner = 2 };
+
 template <typename R, int B>
-static void tile_dispatch_b(const TileArgs &a, bool closed, void *stream) {
+static void tile_dispatch_b(const TileArgs &a, int mode, void *stream) {
     constexpr int RPT = tile_rpt(sizeof(R) == 8, B);
     const size_t lds = (size_t)a.T * B * sizeof(C2<R>);
     const int grid = (int)(a.N / a.T);
-    if (closed)
+    if (mode == kClosed)
         hipLaunchKernelGGL((dia_tile_kernel<R, B, RPT, true>), dim3(grid), dim3(kTileThreads), lds, S(stream), a);
-    else
+    else if (mode == kOpen)
         hipLaunchKernelGGL((dia_tile_kernel<R, B, RPT, false>), dim3(grid), dim3(kTileThreads), lds, S(stream), a);
+    else
+        hipLaunchKernelGGL((dia_tile_kernel<R, B, RPT, false, true>), dim3(grid), dim3(kTileThreads), lds,
+                           S(stream), a);
 }
 
 template <typename R>
-static int tile_dispatch(const TileArgs &a, int batch, bool closed, void *stream) {
+static int tile_dispatch(const TileArgs &a, int batch, int mode, void *stream) {
     switch (batch) {
-        case 1: tile_dispatch_b<R, 1>(a, closed, stream); break;
-        case 2: tile_dispatch_b<R, 2>(a, closed, stream); break;
-        case 3: tile_dispatch_b<R, 3>(a, closed, stream); break;
-        case 4: tile_dispatch_b<R, 4>(a, closed, stream); break;
-        case 5: tile_dispatch_b<R, 5>(a, closed, stream); break;
-        case 6: tile_dispatch_b<R, 6>(a, closed, stream); break;
-        case 7: tile_dispatch_b<R, 7>(a, closed, stream); break;
-        case 8: tile_dispatch_b<R, 8>(a, closed, stream); break;
+        case 1: tile_dispatch_b<R, 1>(a, mode, stream); break;
+        case 2: tile_dispatch_b<R, 2>(a, mode, stream); break;
+        case 3: tile_dispatch_b<R, 3>(a, mode, stream); break;
+        case 4: tile_dispatch_b<R, 4>(a, mode, stream); break;
+        case 5: tile_dispatch_b<R, 5>(a, mode, stream); break;
+        case 6: tile_dispatch_b<R, 6>(a, mode, stream); break;
+        case 7: tile_dispatch_b<R, 7>(a, mode, stream); break;
+        case 8: tile_dispatch_b<R, 8>(a, mode, stream); break;
         default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
 }
 
 int launch_tile(const TileArgs &a, int batch, bool c128, bool closed, void *stream) {
-    return c128 ? tile_dispatch<double>(a, batch, closed, stream)
-                : tile_dispatch<float>(a, batch, closed, stream);
+    const int mode = closed ? kClosed : kOpen;
+    return c128 ? tile_dispatch<double>(a, batch, mode, stream) : tile_dispatch<float>(a, batch, mode, stream);
+}
+
+int launch_tile_horner(const TileArgs &a, int batch, bool c128, void *stream) {
+    if (!a.x0) return (int)hipErrorInvalidValue;
+    return c128 ? tile_dispatch<double>(a, batch, kHorner, stream)
+                : tile_dispatch<float>(a, batch, kHorner, stream);
 }
 
 template <typename R>

@@ -142,3 +142,54 @@ def simulate(strings, coeffs, n, t, psi, budget=None, steps=None, tol=1e-6, max_
     U.close()
     H.close()
     return steps, K, nd
+
+
+def norm_bound(A: DiaOperator, stream=None) -> float:
+    """nu(A): the sum of the per-diagonal largest entry moduli."""
+    v = ctypes.c_double()
+    _lib.check(_lib.load().hs_dia_norm_bound(A.handle, _stream_ptr(stream), ctypes.byref(v)))
+    return v.value
+
+
+def taylor_terms(H: DiaOperator, dt: float, tol: float = 1e-6, max_terms: int = 64, stream=None) -> int:
+    """Smallest K with (|dt| nu(H))^(K+1) / (K+1)! < tol."""
+    k = ctypes.c_int()
+    _lib.check(_lib.load().hs_taylor_terms(H.handle, float(dt), float(tol), int(max_terms),
+                                           _stream_ptr(stream), ctypes.byref(k)))
+    return k.value
+
+
+def taylor_evolve(H: DiaOperator, psi, dt: float, K: int, steps: int, stream=None):
+    """psi <- p_K(-i dt H)^steps psi: the Taylor expansion fused into the state
+    update by Horner's rule (no propagator is formed)."""
+    batch, N, code = _state_args(psi, H.N)
+    if code != H.dtype_code:
+        raise ValueError("state dtype differs from the operator's dtype")
+    _lib.check(_lib.load().hs_taylor_evolve(H.handle, ctypes.c_void_p(psi.data_ptr()), batch, float(dt),
+                                            int(K), int(steps), _stream_ptr(stream)))
+    return psi
+
+
+def taylor_steps(H: DiaOperator, t: float, theta: float = 1.0, stream=None) -> int:
+    """Smallest r with |t / r| nu(H) <= theta."""
+    r = ctypes.c_int()
+    _lib.check(_lib.load().hs_taylor_steps(H.handle, float(t), float(theta), _stream_ptr(stream),
+                                           ctypes.byref(r)))
+    return r.value
+
+
+def taylor_simulate(strings, coeffs, n, t, psi, steps=None, tol=1e-6, theta=1.0, dtype="c128", stream=None):
+    """H from Pauli strings, then r steps of the fused Taylor update with
+    dt = t / r.  r defaults to the smallest with |dt| nu(H) <= theta.
+    Returns (steps, K)."""
+    H = from_pauli(strings, coeffs, n, stream=stream)
+    if steps is None:
+        steps = taylor_steps(H, t, theta, stream=stream)
+    K = taylor_terms(H, t / steps, tol, stream=stream)
+    if dtype_code(dtype) != HS_C128:
+        H64 = H.to_c64(stream=stream)
+        H.close()
+        H = H64
+    taylor_evolve(H, psi, t / steps, K, steps, stream=stream)
+    H.close()
+    return steps, K

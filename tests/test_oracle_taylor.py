@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import scipy.linalg as sl
 
-from oracle import spme, taylor
+from oracle import pauli, spme, taylor
 from workloads import hamiltonians as wh
 
 
@@ -93,3 +93,15 @@ def test_tightening_the_tolerance_converges():
         K = taylor.taylor_terms(H, t / r, tol)
         errs.append(np.linalg.norm(taylor.taylor_evolve(H, psi, t / r, K, r) - exact))
     assert all(a > b for a, b in zip(errs, errs[1:])) and errs[-1] < 1e-12, errs
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_sampled_rows_equal_the_whole_step(K):
+    """The row-sampled form (used at sizes the whole step cannot take) equals
+    the sparse-product step on every row."""
+    Hw = wh.heisenberg_1d(6, 1.0, fields=np.linspace(-1, 1, 6))
+    terms = pauli.parse_terms(Hw.strings, Hw.coeffs, 6)
+    psi = _state(6, 5)
+    whole = taylor.taylor_step(_H(Hw), psi, 0.07, K)
+    rows = np.arange(64)
+    assert np.abs(taylor.step_rows(terms, psi, rows, 0.07, K) - whole).max() < 1e-15
