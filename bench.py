@@ -37,7 +37,9 @@ WORKLOAD = {
     "n_qubits": 26, "J": 1.0, "h": 3.04, "t": 1.0, "trotter_steps": 50, "dt": 0.02,
     "budget": 16, "state": "random_phase_seed3", "batch": 1, "dtype": "complex64",
 }
-KERNEL_SRC = os.path.join(ROOT, "paper_2606_16959_amd", "csrc", "kernels.hip")
+# sources that decide the tile kernel's code and launch plan
+KERNEL_SRC = [os.path.join(ROOT, "paper_2606_16959_amd", "csrc", f)
+              for f in ("kernels.hip", "hs_internal.h", "tile_plan.h", "api.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dia_tile_tfim2d_n26.json")
 OUT_DIR = os.path.join(ROOT, "profiles")      # where summaries are written (--out-dir)
 
@@ -47,8 +49,11 @@ def log(msg):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def launch_bytes(desc, launches, N, batch, elem, seq=None):

@@ -117,12 +117,18 @@ hs_status hs_build_factors(int n_qubits, int n_terms, const char *const *pauli_t
  * hs_evolve -- psi <- (U_F ... U_1)^steps psi, in place, for `batch` states
  * (device pointer to [batch][N] interleaved complex of the factors' dtype).
  * Enqueues kernels on `stream` and returns; faults surface at the caller's
- * next synchronisation.  May be called repeatedly: evolve(k) followed by
- * evolve(steps - k) gives bit-identical results to evolve(steps).
+ * next synchronisation.  May be called repeatedly: for first order,
+ * evolve(k) followed by evolve(steps - k) gives bit-identical results to
+ * evolve(steps) (orders 2 and 4 join consecutive steps of one call in the
+ * joint factor, so a split call differs by rounding only).
  * flags: HS_RENORM (FP64 norm after each step, applied as a scale when the
  * next step loads the state, and once more at the end), HS_NO_FUSE.
  * complex64 states accumulate in FP32 over ascending offsets; complex128 in
  * FP64.  Results do not depend on the batch size or on fusion.
+ * A factor whose coupling range fits no tile held in LDS (e.g. X_0 X_{n-1}
+ * at large n) is applied out of place into a scratch state (allocated on
+ * first use, counted by hs_footprint) and copied back.  Calls that share a
+ * handle share its workspace, so they must be ordered on one stream.
  */
 hs_status hs_evolve(hs_factors f, void *psi, int batch, int steps, void *stream,
                     unsigned flags);

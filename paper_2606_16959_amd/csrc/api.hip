@@ -59,6 +59,8 @@ struct Run {
     Geo geo;
     int launch_batch = 1;       // states per launch (1 when the chunk does not fit)
     bool elementwise = false;   // a single main-diagonal factor
+    bool open = false;          // no closed tile holds the factor's coupling range: open
+                                // launch into the scratch state, then copied back
     int desc_start = 0;
     std::vector<int> dstart;    // per factor, relative to desc_start (size nf + 1)
 };
@@ -83,6 +85,7 @@ std::vector<int> part_sequence(const Plan &P, int part) {
 
 struct EvolvePlan {
     int swizzle = 0;
+    bool needs_scratch = false;  // some run is open
     std::vector<Run> runs[kParts];
     std::vector<DiagDesc> host_desc;
     DiagDesc *dev_desc = nullptr;
@@ -97,6 +100,8 @@ struct hs_factors_s {
     int device = 0;
     int *viol_dev = nullptr;
     double *work_dev = nullptr;      // [8][G][4] partials, then [8][4] records
+    void *scratch_dev = nullptr;     // output of open launches (HS_MAX_BATCH states), on demand
+    size_t scratch_bytes = 0;
     hipStream_t alloc_stream = nullptr;   // device memory is stream-ordered on this stream
     std::map<PlanKey, EvolvePlan> plans;
     std::mutex mu;
@@ -112,6 +117,7 @@ struct hs_factors_s {
         for (auto &kv : plans)
             if (kv.second.dev_desc) (void)hipFreeAsync(kv.second.dev_desc, alloc_stream);
         if (viol_dev) (void)hipFreeAsync(viol_dev, alloc_stream);
+        if (scratch_dev) (void)hipFreeAsync(scratch_dev, alloc_stream);
         if (work_dev) (void)hipFreeAsync(work_dev, alloc_stream);
     }
 };
@@ -125,7 +131,7 @@ hs_status make_evolve_plan(hs_factors_s *h, const PlanKey &key, EvolvePlan &ep, 
     const int n = P.n;
     const int batch = key.chunk;
     const bool fuse = key.fuse != 0;
-    const int Tmax = tile_rows_max(h->dtype, batch);
+    const int Tmax = tile_rows_max(h->dtype, batch, P.N);
     const int Wmin = w_min(h->dtype, key);
     const size_t sc = elem_bytes(h->dtype);
     ep = EvolvePlan();
@@ -170,8 +176,15 @@ hs_status make_evolve_plan(hs_factors_s *h, const PlanKey &key, EvolvePlan &ep, 
             run.geo = geometry(empty ? 0 : lb, empty ? 0 : hb, n, Tmax);
             if (!run.geo.ok) {            // orbit wider than the batched tile: one state per launch
                 run.launch_batch = 1;
-                run.geo = geometry(lb, hb, n, tile_rows_max(h->dtype, 1));
-                if (!run.geo.ok) return fail(HS_ETOOLARGE, "factor coupling range does not fit a tile");
+                run.geo = geometry(lb, hb, n, tile_rows_max(h->dtype, 1, P.N));
+            }
+            if (!run.geo.ok) {            // no closed tile at all (a single factor): open launch
+                const Factor &Fo = P.factors[run.factors[0]];
+                std::vector<long long> o(Fo.offs.begin(), Fo.offs.end());
+                run.launch_batch = batch;
+                run.geo = generic_geometry(o.data(), (int)o.size(), P.N, h->dtype, batch);
+                run.open = true;
+                ep.needs_scratch = true;
             }
             run.desc_start = (int)ep.host_desc.size();
             run.dstart.push_back(0);
@@ -225,7 +238,7 @@ hs_status launch_run(hs_factors_s *h, const EvolvePlan &ep, const Run &run, void
     for (int b0 = 0; b0 < chunk; b0 += lbatch) {
         TileArgs a{};
         char *p = static_cast<char *>(psi) + (size_t)b0 * P.N * sc;
-        a.y = p;
+        a.y = run.open ? h->scratch_dev : p;
         a.x = p;
         a.stride = P.N;
         a.N = (int32_t)P.N;
@@ -238,10 +251,14 @@ hs_status launch_run(hs_factors_s *h, const EvolvePlan &ep, const Run &run, void
         a.nlw_log = run.geo.nlw_log;
         a.T = run.geo.T;
         a.nrm2 = nrm2_records ? nrm2_records + 4 * b0 : nullptr;
-        a.viol = h->viol_dev;
+        a.viol = run.open ? nullptr : h->viol_dev;
         a.swizzle = ep.swizzle;
-        int e = hs::launch_tile(a, std::min(lbatch, chunk - b0), c128, true, stream);
+        const int nb = std::min(lbatch, chunk - b0);
+        int e = hs::launch_tile(a, nb, c128, !run.open, stream);
         if (e) return hip_fail((hipError_t)e, "tile kernel launch");
+        if (run.open)
+            HS_HIP(hipMemcpyAsync(p, h->scratch_dev, (size_t)nb * P.N * sc, hipMemcpyDeviceToDevice,
+                                  reinterpret_cast<hipStream_t>(stream)), "copy back");
     }
     return HS_OK;
 }
@@ -431,6 +448,16 @@ hs_status hs_evolve(hs_factors f, void *psi, int batch, int steps, void *stream,
             it = f->plans.emplace(key, std::move(ep)).first;
         }
         const EvolvePlan &ep = it->second;
+        if (ep.needs_scratch && f->scratch_bytes < (size_t)chunk * P.N * sc) {
+            // stream-ordered: the old buffer's last use precedes this point on `stream`
+            hipStream_t hst = reinterpret_cast<hipStream_t>(stream);
+            if (f->scratch_dev) HS_HIP(hipFreeAsync(f->scratch_dev, hst), "hipFreeAsync(scratch)");
+            f->scratch_dev = nullptr;
+            f->scratch_bytes = 0;
+            const size_t bytes = (size_t)chunk * P.N * sc;
+            HS_HIP(hipMallocAsync(&f->scratch_dev, bytes, hst), "hipMallocAsync(scratch)");
+            f->scratch_bytes = bytes;
+        }
         void *p = static_cast<char *>(psi) + (size_t)c0 * P.N * sc;
         const double *rec = f->records() + 2;    // squared norm of state b at rec[4 b]
         for (int s = 0; s < steps; ++s) {
@@ -599,6 +626,11 @@ hs_status hs_footprint(hs_factors f, int batch, size_t *bytes) {
         }
     }
     total += (size_t)batch * f->plan.N * sc;                         // the states
+    bool open = false;                                                // a factor no closed tile holds
+    for (const auto &F : f->plan.factors)
+        if (F.xmask_union &&
+            !geometry(F.xlb, F.xhb, f->plan.n, tile_rows_max(f->dtype, 1, f->plan.N)).ok) open = true;
+    if (open) total += (size_t)std::min(batch, HS_MAX_BATCH) * f->plan.N * sc;   // its scratch state
     total += sizeof(double) * ((size_t)HS_MAX_BATCH * hs::kReduceBlocks * 4 + HS_MAX_BATCH * 4);
     total += 64 * 1024;                                               // descriptors, flag
     *bytes = total;

@@ -165,7 +165,10 @@ constexpr int kReduceBlocks = 1024;   // partial sums per state (fixed: determin
 #define HS_TILE_THREADS 512
 #endif
 #ifndef HS_TILE_ACC_C64
-#define HS_TILE_ACC_C64 8      // complex accumulators per thread (rows x batch), complex64
+#define HS_TILE_ACC_C64 16     // complex accumulators per thread (rows x batch), complex64
+#endif
+#ifndef HS_TILE_ACC_C64_OPEN
+#define HS_TILE_ACC_C64_OPEN 8 // the same for open launches (out-of-tile gathers want more waves)
 #endif
 #ifndef HS_TILE_ACC_C128
 #define HS_TILE_ACC_C128 4     // same for complex128
@@ -177,15 +180,15 @@ constexpr int kTileThreads = HS_TILE_THREADS;
 
 // Rows per thread for a launch of `batch` states: the accumulator budget
 // split over the batch rounded up to a power of two, at least one row pair.
-constexpr int tile_rpt(bool c128, int batch) {
+constexpr int tile_rpt(bool c128, int batch, bool open = false) {
     int bp = 1;
     while (bp < batch) bp <<= 1;
-    const int acc = c128 ? HS_TILE_ACC_C128 : HS_TILE_ACC_C64;
+    const int acc = c128 ? HS_TILE_ACC_C128 : (open ? HS_TILE_ACC_C64_OPEN : HS_TILE_ACC_C64);
     return acc / bp >= 2 ? acc / bp : 2;
 }
 // Rows of the largest tile: all threads' rows, capped by the LDS budget.
-constexpr int tile_rows_cap(bool c128, int batch) {
-    const int rows = kTileThreads * tile_rpt(c128, batch);
+constexpr int tile_rows_cap(bool c128, int batch, bool open = false) {
+    const int rows = kTileThreads * tile_rpt(c128, batch, open);
     const int lds_rows = HS_TILE_LDS_BYTES / (batch * (c128 ? 16 : 8));
     int cap = 1;
     while (cap * 2 <= rows && cap * 2 <= lds_rows) cap *= 2;

@@ -519,34 +519,49 @@ int launch_construct(const ConstructArgs &a, int nd, int64_t max_len, bool c128,
 
 enum TileMode { kOpen = 0, kClosed = 1, kHorner = 2 };
 
+// Launch with the smallest rows-per-thread instantiation (power of two, down
+// to one row pair) that still gives every tile row a thread: a tile smaller
+// than the kernel's capacity would otherwise issue masked loads and FMAs.
+template <typename R, int B, int RPT, bool CLOSED, bool HORNER>
+static int tile_launch(const TileArgs &a, int rows_per_thread, size_t lds, int grid, void *stream) {
+    if constexpr (RPT > 2) {
+        if (rows_per_thread <= RPT / 2)
+            return tile_launch<R, B, RPT / 2, CLOSED, HORNER>(a, rows_per_thread, lds, grid, stream);
+    }
+    hipLaunchKernelGGL((dia_tile_kernel<R, B, RPT, CLOSED, HORNER>), dim3(grid), dim3(kTileThreads), lds,
+                       S(stream), a);
+    return (int)hipGetLastError();
+}
+
 template <typename R, int B>
-static void tile_dispatch_b(const TileArgs &a, int mode, void *stream) {
+static int tile_dispatch_b(const TileArgs &a, int mode, void *stream) {
     constexpr int RPT = tile_rpt(sizeof(R) == 8, B);
+    constexpr int RPT_OPEN = tile_rpt(sizeof(R) == 8, B, true);
     const size_t lds = (size_t)a.T * B * sizeof(C2<R>);
     const int grid = (int)(a.N / a.T);
-    if (mode == kClosed)
-        hipLaunchKernelGGL((dia_tile_kernel<R, B, RPT, true>), dim3(grid), dim3(kTileThreads), lds, S(stream), a);
-    else if (mode == kOpen)
-        hipLaunchKernelGGL((dia_tile_kernel<R, B, RPT, false>), dim3(grid), dim3(kTileThreads), lds, S(stream), a);
-    else
-        hipLaunchKernelGGL((dia_tile_kernel<R, B, RPT, false, true>), dim3(grid), dim3(kTileThreads), lds,
-                           S(stream), a);
+    // every tile row must belong to a thread, and the tile must fit the LDS budget
+    const int rpt = mode == kClosed ? RPT : RPT_OPEN;
+    if (a.T < 2 || a.T > kTileThreads * rpt || lds > (size_t)HS_TILE_LDS_BYTES || a.N % a.T)
+        return (int)hipErrorInvalidValue;
+    const int need = (a.T + kTileThreads - 1) / kTileThreads;
+    if (mode == kClosed) return tile_launch<R, B, RPT, true, false>(a, need, lds, grid, stream);
+    if (mode == kOpen) return tile_launch<R, B, RPT_OPEN, false, false>(a, need, lds, grid, stream);
+    return tile_launch<R, B, RPT_OPEN, false, true>(a, need, lds, grid, stream);
 }
 
 template <typename R>
 static int tile_dispatch(const TileArgs &a, int batch, int mode, void *stream) {
     switch (batch) {
-        case 1: tile_dispatch_b<R, 1>(a, mode, stream); break;
-        case 2: tile_dispatch_b<R, 2>(a, mode, stream); break;
-        case 3: tile_dispatch_b<R, 3>(a, mode, stream); break;
-        case 4: tile_dispatch_b<R, 4>(a, mode, stream); break;
-        case 5: tile_dispatch_b<R, 5>(a, mode, stream); break;
-        case 6: tile_dispatch_b<R, 6>(a, mode, stream); break;
-        case 7: tile_dispatch_b<R, 7>(a, mode, stream); break;
-        case 8: tile_dispatch_b<R, 8>(a, mode, stream); break;
+        case 1: return tile_dispatch_b<R, 1>(a, mode, stream);
+        case 2: return tile_dispatch_b<R, 2>(a, mode, stream);
+        case 3: return tile_dispatch_b<R, 3>(a, mode, stream);
+        case 4: return tile_dispatch_b<R, 4>(a, mode, stream);
+        case 5: return tile_dispatch_b<R, 5>(a, mode, stream);
+        case 6: return tile_dispatch_b<R, 6>(a, mode, stream);
+        case 7: return tile_dispatch_b<R, 7>(a, mode, stream);
+        case 8: return tile_dispatch_b<R, 8>(a, mode, stream);
         default: return (int)hipErrorInvalidValue;
     }
-    return (int)hipGetLastError();
 }
 
 int launch_tile(const TileArgs &a, int batch, bool c128, bool closed, void *stream) {

@@ -26,8 +26,14 @@ struct Geo {
     bool ok = false;
 };
 
-// Largest tile (rows) one launch of `batch` states holds.
-inline int tile_rows_max(int dtype, int batch) { return tile_rows_cap(dtype == HS_C128, batch); }
+// Largest tile (rows) one launch of `batch` states over N rows uses: the
+// kernel's capacity (closed or open launch), halved (down to 1024 rows) while
+// the grid would have fewer than 256 tiles, one per compute unit.
+inline int tile_rows_max(int dtype, int batch, long long N, bool open = false) {
+    int T = tile_rows_cap(dtype == HS_C128, batch, open);
+    while (T > 1024 && N / T < 256) T >>= 1;
+    return T;
+}
 
 // Launch-plan tuning knobs, read from the environment at every evolve (a
 // handle keeps one plan per batch size and knob setting): HAMSIM_WMIN_BYTES (shortest run of consecutive rows a
@@ -88,7 +94,7 @@ inline Geo generic_geometry(const long long *offsets, int nd, long long N, int d
         maxabs = std::max(maxabs, a);
     }
     const int n = ilog2(N);
-    const int Tmax = tile_rows_max(dtype, chunk);
+    const int Tmax = tile_rows_max(dtype, chunk, N, true);
     const PlanKey key = plan_key(chunk, true);
     const int q = orall ? __builtin_ctzll(orall) : 0;
     Geo geo = geometry(0, 0, n, Tmax);

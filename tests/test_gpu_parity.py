@@ -367,3 +367,43 @@ def test_higher_order_products_match_oracle(order):
     assert fid(p.cpu().numpy()[0].astype(np.complex128), ref) >= 1 - 1e-6
     assert f.check_closure()
     f.close()
+
+
+# ------------------------------------------------------------------ long-range factors
+
+@pytest.mark.parametrize("n,dtype", [(16, "c128"), (20, "c64")])
+def test_long_range_factor_takes_an_open_launch(n, dtype):
+    """A periodic chain's closing bond X_0 X_{n-1} + Y_0 Y_{n-1} couples bits 0
+    and n-1, wider than any tile held in LDS: that factor runs as an open
+    launch into the scratch state.  Same oracle bar; fusion and batching stay
+    bit-exact."""
+    hs, torch = hs_gpu()
+    H = wh.heisenberg_1d(n, 1.0, fields=np.linspace(-1, 1, n), periodic=True)
+    npd = np.complex128 if dtype == "c128" else np.complex64
+    note(f"periodic heisenberg n={n} {dtype} (open launch)")
+    f = hs.build_factors(H.strings, H.coeffs, n, 1.0, 20, 16, dtype=dtype)
+    fac = f.describe()["factors"]
+    wide = [k for k, x in enumerate(fac) if x["support_mask"] & 1 and x["support_mask"] >> (n - 1) & 1]
+    assert wide, "the closing bond should form a factor over qubits 0 and n-1"
+    desc_bytes = sum(x["bytes"] for x in fac)
+    elem = 16 if dtype == "c128" else 8
+    assert f.footprint(1) >= desc_bytes + 2 * (1 << n) * elem        # state + scratch
+    psi0 = np.stack([ws.neel_state(n, npd), ws.random_phase_state(n, 5, npd), ws.zero_state(n, npd)])
+    p = _to_dev(torch, psi0, npd)
+    hs.evolve(f, p, 6)
+    terms = opauli.parse_terms(H.strings, H.coeffs, n)
+    part = ofac.first_fit(terms, 16, 0.05)
+    from oracle import evolve as oev
+    ref = oev.evolve(terms, part, psi0.astype(np.complex128), n, 0.05, 6, threads=oracle_threads())
+    got = p.cpu().numpy().astype(np.complex128)
+    if dtype == "c128":
+        assert np.abs(got - ref).max() <= 1e-12
+    assert np.all(fid(got, ref) >= (1 - 1e-12 if dtype == "c128" else 1 - 1e-6))
+    q = _to_dev(torch, psi0, npd)
+    hs.evolve(f, q, 6, fuse=False)
+    assert np.array_equal(p.cpu().numpy(), q.cpu().numpy())
+    single = _to_dev(torch, psi0[1:2], npd)
+    hs.evolve(f, single, 6)
+    assert np.array_equal(single.cpu().numpy()[0], p.cpu().numpy()[1])
+    assert f.check_closure()
+    f.close()
