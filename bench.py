@@ -231,6 +231,7 @@ SWEEP = [
     ("wmin512", {"HAMSIM_WMIN_BYTES": "512"}),
     ("wmin512_no_swizzle", {"HAMSIM_WMIN_BYTES": "512", "HAMSIM_XCD_SWIZZLE": "0"}),
     ("wmin1024", {"HAMSIM_WMIN_BYTES": "1024"}),
+    ("wmin2048", {"HAMSIM_WMIN_BYTES": "2048"}),
     ("fuse1", {"HAMSIM_MAX_FUSE": "1"}),
     ("fuse3", {"HAMSIM_MAX_FUSE": "3"}),
 ]

@@ -1,6 +1,8 @@
 // Launch planning shared by the factor and operator APIs (host only).
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <algorithm>
 #include <cstdint>
 #include <cstdlib>
@@ -26,11 +28,24 @@ struct Geo {
     bool ok = false;
 };
 
+// LDS a tile may use: the compile-time budget, capped by the current
+// device's per-workgroup limit (queried once).
+inline int lds_budget() {
+    static const int v = [] {
+        int dev = 0, lim = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lim <= 0)
+            lim = 65536;
+        return std::min(lim, (int)HS_TILE_LDS_BYTES);
+    }();
+    return v;
+}
+
 // Largest tile (rows) one launch of `batch` states over N rows uses: the
 // kernel's capacity (closed or open launch), halved (down to 1024 rows) while
 // the grid would have fewer than 256 tiles, one per compute unit.
 inline int tile_rows_max(int dtype, int batch, long long N, bool open = false) {
-    int T = tile_rows_cap(dtype == HS_C128, batch, open);
+    int T = tile_rows_cap(dtype == HS_C128, batch, open, lds_budget());
     while (T > 1024 && N / T < 256) T >>= 1;
     return T;
 }
