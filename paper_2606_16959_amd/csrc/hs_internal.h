@@ -174,25 +174,28 @@ constexpr int kReduceBlocks = 1024;   // partial sums per state (fixed: determin
 #define HS_TILE_ACC_C128 4     // same for complex128
 #endif
 #ifndef HS_TILE_LDS_BYTES
-#define HS_TILE_LDS_BYTES 65536  // largest staged tile (all states); the planner also
+#define HS_TILE_LDS_BYTES 131072 // largest staged tile (all states); the planner also
                                  // respects the device's per-workgroup LDS limit
 #endif
 constexpr int kTileThreads = HS_TILE_THREADS;
 
 // Rows per thread for a launch of `batch` states: the accumulator budget
 // split over the batch rounded up to a power of two, at least one row pair.
-// (Closed 8-state tiles of 2048 rows fit the registers with two pairs and
-// 128 KiB of LDS, but one workgroup per CU then runs slower per byte than
-// 1024-row tiles, even though it saves launches.)
 constexpr int tile_rpt(bool c128, int batch, bool open = false) {
     int bp = 1;
     while (bp < batch) bp <<= 1;
     const int acc = c128 ? HS_TILE_ACC_C128 : (open ? HS_TILE_ACC_C64_OPEN : HS_TILE_ACC_C64);
     return acc / bp >= 2 ? acc / bp : 2;
 }
+// Threads per workgroup: closed complex64 launches of 5-8 states use twice
+// the default, so a 2048-row tile (128 KiB of LDS, one workgroup per CU) still
+// runs 16 waves per CU with one row pair per thread.
+constexpr int tile_threads(bool c128, int batch, bool open = false) {
+    return (!c128 && !open && batch > 4) ? 2 * kTileThreads : kTileThreads;
+}
 // Rows of the largest tile: all threads' rows, capped by an LDS budget.
 constexpr int tile_rows_cap(bool c128, int batch, bool open = false, int lds_bytes = HS_TILE_LDS_BYTES) {
-    const int rows = kTileThreads * tile_rpt(c128, batch, open);
+    const int rows = tile_threads(c128, batch, open) * tile_rpt(c128, batch, open);
     const int lds_rows = lds_bytes / (batch * (c128 ? 16 : 8));
     int cap = 1;
     while (cap * 2 <= rows && cap * 2 <= lds_rows) cap *= 2;

@@ -225,11 +225,10 @@ __device__ __forceinline__ void load_diag(C2<R> (&c)[P][2], const DiagDesc &dd, 
 
 // HORNER (open launches only): the output row is x0[r] + alpha * (A x)[r],
 // one Horner stage of a polynomial in A applied to a state.
-template <typename R, int B, int RPT, bool CLOSED, bool HORNER = false>
-__global__ __launch_bounds__(kTileThreads) void dia_tile_kernel(TileArgs a) {
+template <typename R, int B, int RPT, bool CLOSED, bool HORNER = false, int NT = kTileThreads>
+__global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
     static_assert(RPT % 2 == 0, "rows come in pairs");
     constexpr int P = RPT / 2;
-    constexpr int NT = kTileThreads;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<R> *lds = reinterpret_cast<C2<R> *>(smem_raw);
     const int T = a.T;
@@ -522,31 +521,42 @@ enum TileMode { kOpen = 0, kClosed = 1, kHorner = 2 };
 // Launch with the smallest rows-per-thread instantiation (power of two, down
 // to one row pair) that still gives every tile row a thread: a tile smaller
 // than the kernel's capacity would otherwise issue masked loads and FMAs.
-template <typename R, int B, int RPT, bool CLOSED, bool HORNER>
+template <typename R, int B, int RPT, bool CLOSED, bool HORNER, int NT>
 static int tile_launch(const TileArgs &a, int rows_per_thread, size_t lds, int grid, void *stream) {
     if constexpr (RPT > 2) {
         if (rows_per_thread <= RPT / 2)
-            return tile_launch<R, B, RPT / 2, CLOSED, HORNER>(a, rows_per_thread, lds, grid, stream);
+            return tile_launch<R, B, RPT / 2, CLOSED, HORNER, NT>(a, rows_per_thread, lds, grid, stream);
     }
-    hipLaunchKernelGGL((dia_tile_kernel<R, B, RPT, CLOSED, HORNER>), dim3(grid), dim3(kTileThreads), lds,
-                       S(stream), a);
+    auto kern = dia_tile_kernel<R, B, RPT, CLOSED, HORNER, NT>;
+    if (lds > 65536) {
+        // this instantiation may take more than 64 KiB of dynamic LDS
+        static const hipError_t set = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                          (int)HS_TILE_LDS_BYTES);
+        if (set != hipSuccess) return (int)set;
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, S(stream), a);
     return (int)hipGetLastError();
 }
 
 template <typename R, int B>
 static int tile_dispatch_b(const TileArgs &a, int mode, void *stream) {
-    constexpr int RPT = tile_rpt(sizeof(R) == 8, B);
-    constexpr int RPT_OPEN = tile_rpt(sizeof(R) == 8, B, true);
+    constexpr bool c128 = sizeof(R) == 8;
+    constexpr int RPT = tile_rpt(c128, B);
+    constexpr int RPT_OPEN = tile_rpt(c128, B, true);
+    constexpr int NTC = tile_threads(c128, B);
+    constexpr int NTO = tile_threads(c128, B, true);
     const size_t lds = (size_t)a.T * B * sizeof(C2<R>);
     const int grid = (int)(a.N / a.T);
     // every tile row must belong to a thread, and the tile must fit the LDS budget
+    const int nt = mode == kClosed ? NTC : NTO;
     const int rpt = mode == kClosed ? RPT : RPT_OPEN;
-    if (a.T < 2 || a.T > kTileThreads * rpt || lds > (size_t)HS_TILE_LDS_BYTES || a.N % a.T)
+    if (a.T < 2 || a.T > nt * rpt || lds > (size_t)HS_TILE_LDS_BYTES || a.N % a.T)
         return (int)hipErrorInvalidValue;
-    const int need = (a.T + kTileThreads - 1) / kTileThreads;
-    if (mode == kClosed) return tile_launch<R, B, RPT, true, false>(a, need, lds, grid, stream);
-    if (mode == kOpen) return tile_launch<R, B, RPT_OPEN, false, false>(a, need, lds, grid, stream);
-    return tile_launch<R, B, RPT_OPEN, false, true>(a, need, lds, grid, stream);
+    const int need = (a.T + nt - 1) / nt;
+    if (mode == kClosed) return tile_launch<R, B, RPT, true, false, NTC>(a, need, lds, grid, stream);
+    if (mode == kOpen) return tile_launch<R, B, RPT_OPEN, false, false, NTO>(a, need, lds, grid, stream);
+    return tile_launch<R, B, RPT_OPEN, false, true, NTO>(a, need, lds, grid, stream);
 }
 
 template <typename R>
