@@ -191,7 +191,7 @@ constexpr int tile_rpt(bool c128, int batch, bool open = false) {
 // the default, so a 2048-row tile (128 KiB of LDS, one workgroup per CU) still
 // runs 16 waves per CU with one row pair per thread.
 constexpr int tile_threads(bool c128, int batch, bool open = false) {
-    return (!c128 && !open && batch > 2) ? 2 * kTileThreads : kTileThreads;
+    return (!c128 && (open || batch > 2)) ? 2 * kTileThreads : kTileThreads;
 }
 // Rows of the largest tile: all threads' rows, capped by an LDS budget.
 constexpr int tile_rows_cap(bool c128, int batch, bool open = false, int lds_bytes = HS_TILE_LDS_BYTES) {
