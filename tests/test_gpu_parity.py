@@ -407,3 +407,32 @@ def test_long_range_factor_takes_an_open_launch(n, dtype):
     assert np.array_equal(single.cpu().numpy()[0], p.cpu().numpy()[1])
     assert f.check_closure()
     f.close()
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_higher_order_full_size_config3(order):
+    """The n = 26 workload with the bench's launch plan, 3 steps (first,
+    middle and last step lists, joint factors included), against the
+    oracle's unmerged product on the full state."""
+    hs, torch = hs_gpu()
+    from oracle import evolve as oev
+    note(f"order {order}: config3 n=26 c64, 3 of 50 steps, vs oracle")
+    H = config_hamiltonian(3)
+    psi0 = ws.random_phase_state(26, 3, np.complex64)
+    f = hs.build_factors(H.strings, H.coeffs, 26, 1.0, 50, 16, dtype="c64", order=order)
+    desc = f.describe()
+    applications = sum(len(f.part_sequence(q, desc)) for q in (1, 2, 3))
+    p = _to_dev(torch, psi0[None], np.complex64)
+    hs.evolve(f, p, 3)
+    got = p.cpu().numpy()[0].astype(np.complex128)
+    f.close()
+    del p
+    terms = opauli.parse_terms(H.strings, H.coeffs, 26)
+    part = ofac.first_fit(terms, 16, 0.02)
+    ref = oev.evolve(terms, part, psi0.astype(np.complex128), 26, 0.02, 3, order=order,
+                     threads=oracle_threads())
+    assert fid(got, ref) >= 1 - 1e-6
+    # each complex64 factor application (unitary, <= 15 diagonals, FP32
+    # accumulation, coefficients rounded once) adds at most a few 2^-24 of
+    # the row scale; the errors add over the applications
+    assert np.abs(got - ref).max() <= applications * 2.0 ** -22 * np.abs(ref).max()

@@ -6,7 +6,7 @@ import pytest
 
 from gpu_common import fid, hs_gpu, note
 from oracle import dia as odia, pauli as opauli, spme as ospme
-from workloads import hamiltonians as wh
+from workloads import hamiltonians as wh, states as ws
 
 pytestmark = pytest.mark.gpu
 
@@ -152,3 +152,34 @@ def test_diagonal_hamiltonian_single_step_is_exact():
     terms = opauli.parse_terms(Hw.strings, Hw.coeffs, 10)
     E = np.real(np.diag(opauli.dense_hamiltonian(terms, 10)))
     assert np.abs(psi.cpu().numpy() - np.exp(-0.8j * E) * psi0).max() <= 1e-14
+
+
+def test_single_propagator_full_size_sampled_rows():
+    """The bench's n = 24 chain (budget 2n + 1): the searched r keeps K = 1,
+    so U x = x - i dt H x, the first-order Taylor step, which the oracle
+    evaluates on sampled rows (ends, tile edges, random) from the Pauli
+    action.  One complex64 SpMV of the open-tile Alg. 3 loop."""
+    hd, torch = _dia()
+    from oracle import taylor as otay
+    n = 24
+    Hw = wh.tfim_1d(n, 1.0, 1.0)
+    note("single propagator n=24 c64 (full size, sampled rows)")
+    H = hd.from_pauli(Hw.strings, Hw.coeffs, n)
+    r = hd.estimate_timesteps(H, 1.0, 2 * n + 1)
+    U, K = hd.spme(H, 1.0 / r)
+    assert K == 1 and U.n_diags == 2 * n + 1
+    U64 = U.to_c64()
+    U.close()
+    H.close()
+    x0 = ws.random_phase_state(n, 7, np.complex64)
+    psi = torch.from_numpy(x0.copy()).cuda()
+    hd.evolve(U64, psi, 1)
+    got = psi.cpu().numpy()
+    U64.close()
+    N = 1 << n
+    rng = np.random.default_rng(1)
+    rows = np.unique(np.concatenate([np.arange(64), N - 1 - np.arange(64), 8192 * np.arange(1, 64) - 1,
+                                     8192 * np.arange(1, 64), rng.integers(0, N, 2048)]))
+    terms = opauli.parse_terms(Hw.strings, Hw.coeffs, n)
+    ref = otay.step_rows(terms, x0.astype(np.complex128), rows, 1.0 / r, 1)
+    assert np.abs(got[rows].astype(np.complex128) - ref).max() <= 2.0 ** -20 * np.abs(x0).max() * 4
