@@ -115,6 +115,7 @@ def cpu_baseline(H, psi0_c64, budget, t, steps_total, sample_steps, step_bytes):
     oev.evolve(terms, part, psi, H.n, t / steps_total, sample_steps)
     t2 = time.perf_counter()
     per_step = ((t2 - t1) - (t1 - t0)) / sample_steps
+    ref = oev.evolve(terms, part, psi, H.n, t / steps_total, sample_steps)
     return {
         "value": round(step_bytes / per_step / 1e9, 3), "unit": "GB/s",
         "cores": threads, "kind": "oracle",
@@ -122,7 +123,17 @@ def cpu_baseline(H, psi0_c64, budget, t, steps_total, sample_steps, step_bytes):
                   f"(C + OpenMP, {threads} threads); setup (phase table, {t1 - t0:.2f} s) excluded; "
                   f"value = the step's algorithmic DIA bytes / oracle step time",
         "ms_per_step": round(per_step * 1e3, 1),
-    }
+    }, ref
+
+
+def accuracy(got, ref):
+    """Error of GPU states against reference states ([B, N] or [N])."""
+    from oracle import metrics
+    g = np.atleast_2d(np.asarray(got, dtype=np.complex128))
+    r = np.atleast_2d(np.asarray(ref, dtype=np.complex128))
+    fid = metrics.fidelity(g, r)
+    return {"min_fidelity": float(np.min(fid)), "max_abs_err": float(np.abs(g - r).max()),
+            "max_norm_drift": float(np.max(np.abs(np.linalg.norm(g, axis=1) - 1.0)))}
 
 
 def serve_leg(torch, n_jobs, rate, slots, oracle_nmax):
@@ -309,6 +320,9 @@ def sweep(torch, steps, warmup, rounds=3):
     print("\n".join(md))
 
 
+ACCURACY_STEPS = {1: 10, 2: 100, 4: 2}      # whole runs for configs 1 and 2; 2 steps at n = 24, B = 8
+
+
 def other_configs(torch, steps=10, warmup=2):
     """The other workload configurations in the same harness: per-step time
     and algorithmic GB/s (n <= 20 states stay in the 256 MB last-level cache,
@@ -316,7 +330,9 @@ def other_configs(torch, steps=10, warmup=2):
     import paper_2606_16959_amd as hs
     from workloads import config_hamiltonian, states as ws
     from workloads.hamiltonians import CONFIG_RUN
+    from oracle import evolve as oev, factors as ofac, pauli as opauli
     out = []
+    oracle_refs, c128_states = {}, {}
     cases = [(1, "c128", False), (2, "c128", False), (2, "c64", False), (4, "c64", False),
              (3, "c64", True)]
     for cfg, dtype, renorm in cases:
@@ -344,6 +360,24 @@ def other_configs(torch, steps=10, warmup=2):
                "gb_per_step": round(sum(per) / 1e9, 3), "gbs": round(sum(per) / ms / 1e6, 1)}
         if B > 1:
             row["ms_per_state_step"] = round(ms / B, 4)
+        if cfg in ACCURACY_STEPS:
+            # error against the FP64 oracle over the first k steps from the
+            # configuration's initial states (complex64 also against complex128)
+            k = ACCURACY_STEPS[cfg]
+            psi0 = np.ascontiguousarray(ws.config_states(cfg, np.complex128))
+            if cfg not in oracle_refs:
+                terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
+                part = ofac.first_fit(terms, run["budget"], run["t"] / run["steps"])
+                oracle_refs[cfg] = oev.evolve(terms, part, psi0, H.n, run["t"] / run["steps"], k)
+            pa = torch.from_numpy(psi0.astype(npd)).cuda()
+            hs.evolve(f, pa, k)
+            got = pa.cpu().numpy()
+            row["accuracy_vs_oracle"] = dict(accuracy(got, oracle_refs[cfg]), steps=k)
+            if dtype == "c128":
+                c128_states[cfg] = got
+            elif cfg in c128_states:
+                row["fidelity_vs_c128_gpu"] = accuracy(got, c128_states[cfg])["min_fidelity"]
+            del pa
         out.append(row)
         log(f"config {cfg} {dtype} B={B} renorm={renorm}: {ms:.4f} ms/step {row['gbs']} GB/s")
         f.close()
@@ -636,8 +670,14 @@ def main():
     cpu = None
     if args.cpu_steps > 0:
         log(f"oracle sample: {args.cpu_steps} steps at n=26 on the host")
-        cpu = cpu_baseline(H, psi0, budget, t, steps_total, args.cpu_steps, step_bytes)
+        cpu, ref = cpu_baseline(H, psi0, budget, t, steps_total, args.cpu_steps, step_bytes)
         log(f"oracle {cpu['ms_per_step']} ms/step ({cpu['cores']} threads)")
+        # the same steps on the GPU from the same state: error against the oracle
+        pa = torch.from_numpy(psi0.copy()).cuda()
+        hs.evolve(f, pa, args.cpu_steps, renorm=args.renorm, fuse=not args.no_fuse)
+        extra["accuracy_vs_oracle"] = dict(accuracy(pa.cpu().numpy(), ref), steps=args.cpu_steps)
+        log(f"vs oracle after {args.cpu_steps} steps: {extra['accuracy_vs_oracle']}")
+        del pa, ref
 
     others = None
     if not args.no_other_configs:

@@ -436,3 +436,23 @@ def test_higher_order_full_size_config3(order):
     # accumulation, coefficients rounded once) adds at most a few 2^-24 of
     # the row scale; the errors add over the applications
     assert np.abs(got - ref).max() <= applications * 2.0 ** -22 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("cfg,steps", [(2, 100), (4, 5)])
+def test_complex64_matches_the_complex128_path(cfg, steps):
+    """The complex64 path against the plain complex128 GPU path on the same
+    inputs (config 2: the whole run; config 4: 8 batched states)."""
+    hs, torch = hs_gpu()
+    H = config_hamiltonian(cfg)
+    run = wh.CONFIG_RUN[cfg]
+    psi0 = np.ascontiguousarray(ws.config_states(cfg, np.complex128))
+    note(f"config {cfg}: complex64 vs complex128, {steps} steps")
+    out = {}
+    for dtype, npd in (("c128", np.complex128), ("c64", np.complex64)):
+        f = hs.build_factors(H.strings, H.coeffs, H.n, run["t"], run["steps"], run["budget"], dtype=dtype)
+        p = _to_dev(torch, psi0, npd)
+        hs.evolve(f, p, steps)
+        out[dtype] = p.cpu().numpy().astype(np.complex128)
+        f.close()
+        del p
+    assert np.all(fid(out["c64"], out["c128"]) >= 1 - 1e-6)

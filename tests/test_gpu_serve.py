@@ -42,6 +42,13 @@ def test_alone_equals_mixed_bitwise_and_matches_oracle():
         ref = oracle_run(spec.hamiltonian(), j.budget, j.t, j.steps, r.psi0.astype(np.complex128))
         assert np.all(fid(r.psi.astype(np.complex128), ref) >= 1 - 1e-6), (spec.family, spec.n)
         assert np.all(np.abs(r.norm2 - 1.0) < 1e-4)
+    note("serve: the served complex64 results against the plain complex128 path")
+    for j, r in list(zip(jobs, mixed))[:4]:
+        f = hs.build_factors(j.strings, j.coeffs, j.n, j.t, j.steps, j.budget, dtype="c128")
+        p = torch.from_numpy(r.psi0.astype(np.complex128)).cuda()
+        hs.evolve(f, p, j.steps)
+        f.close()
+        assert np.all(fid(r.psi.astype(np.complex128), p.cpu().numpy()) >= 1 - 1e-6), j.job_id
 
 
 def test_tight_budget_serialises_but_completes():
