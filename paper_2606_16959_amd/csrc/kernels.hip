@@ -6,6 +6,9 @@
 // LDS staging of the state tile and wave64 shuffle reductions.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <mutex>
+
 #include "hs_internal.h"
 
 namespace hs {
@@ -518,6 +521,11 @@ int launch_construct(const ConstructArgs &a, int nd, int64_t max_len, bool c128,
 
 enum TileMode { kOpen = 0, kClosed = 1, kHorner = 2 };
 
+static std::mutex &lds_attr_mutex() {
+    static std::mutex m;
+    return m;
+}
+
 // Launch with the smallest rows-per-thread instantiation (power of two, down
 // to one row pair) that still gives every tile row a thread: a tile smaller
 // than the kernel's capacity would otherwise issue masked loads and FMAs.
@@ -529,11 +537,21 @@ static int tile_launch(const TileArgs &a, int rows_per_thread, size_t lds, int g
     }
     auto kern = dia_tile_kernel<R, B, RPT, CLOSED, HORNER, NT>;
     if (lds > 65536) {
-        // this instantiation may take more than 64 KiB of dynamic LDS
-        static const hipError_t set = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                          (int)HS_TILE_LDS_BYTES);
-        if (set != hipSuccess) return (int)set;
+        // allow this instantiation the dynamic LDS the launch needs (raised
+        // only when a larger launch arrives; the planner keeps lds within the
+        // device's per-workgroup limit)
+        static std::atomic<int> allowed{65536};
+        int cur = allowed.load();
+        while ((int)lds > cur) {
+            std::lock_guard<std::mutex> lock(lds_attr_mutex());
+            cur = allowed.load();
+            if ((int)lds <= cur) break;
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return (int)e;
+            allowed.store((int)lds);
+            cur = (int)lds;
+        }
     }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, S(stream), a);
     return (int)hipGetLastError();
