@@ -193,7 +193,11 @@ hs_status hs_free_factors(hs_factors f);
  *   offsets     host array, strictly ascending, each in (-N, N)
  *   diags       host array of n_diags device pointers; diags[j] holds
  *               N - |offsets[j]| entries of `dtype`
- *   x, y        device, [batch][N]; must not overlap
+ *   x, y        device, [batch][N]; must not overlap; x, y and every
+ *               diagonal start on a 16-byte boundary
+ *   N           any size in [1, 2^30] (a power of two takes the LDS tiles
+ *               with strided shapes; any other N contiguous tiles, the last
+ *               one partial)
  * Rows accumulate diagonals in ascending-offset order.
  */
 hs_status hs_dia_spmv(int n_diags, const long long *offsets, const void *const *diags,
@@ -232,9 +236,9 @@ typedef struct hs_dia_s *hs_dia;
  * and coefficient conventions as hs_plan.  Synchronises `stream`. */
 hs_status hs_dia_from_pauli(int n_qubits, int n_terms, const char *const *pauli_terms,
                             const double *coeffs, void *stream, hs_dia *out);
-/* An operator from host diagonals: host_diags[j] holds N - |offsets[j]|
- * complex128 entries (interleaved re, im), storage index min(row, col);
- * offsets strictly ascending.  Synchronises `stream`. */
+/* An operator of any size N in [1, 2^30] from host diagonals: host_diags[j]
+ * holds N - |offsets[j]| complex128 entries (interleaved re, im), storage
+ * index min(row, col); offsets strictly ascending.  Synchronises `stream`. */
 hs_status hs_dia_from_host(long long N, int n_diags, const long long *offsets,
                            const double *const *host_diags, void *stream, hs_dia *out);
 hs_status hs_dia_info(hs_dia A, long long *N, int *n_diags, int *dtype);

@@ -659,8 +659,7 @@ hs_status hs_dia_spmv(int n_diags, const long long *offsets, const void *const *
     if (dtype != HS_C64 && dtype != HS_C128) return fail(HS_EINVAL, "bad dtype");
     if (n_diags < 1 || n_diags > 65535 || !offsets || !diags || !x || !y || batch < 1)
         return fail(HS_EINVAL, "bad arguments");
-    if (N < 1 || N > (1ll << HS_MAX_QUBITS) || (N & (N - 1)))
-        return fail(HS_EINVAL, "N must be a power of two <= 2^30");
+    if (N < 1 || N > (1ll << HS_MAX_QUBITS)) return fail(HS_EINVAL, "N must be in [1, 2^30]");
     const size_t sc = elem_bytes(dtype);
     const char *xb = static_cast<const char *>(x);
     char *yb = static_cast<char *>(y);

@@ -448,7 +448,7 @@ hs_status hs_dia_from_host(long long N, int n_diags, const long long *offsets, c
                            void *stream, hs_dia *out) {
     if (!out) return dfail(HS_EINVAL, "null output");
     *out = nullptr;
-    if (N < 1 || N > (1ll << HS_MAX_QUBITS) || (N & (N - 1))) return dfail(HS_EINVAL, "N must be a power of two <= 2^30");
+    if (N < 1 || N > (1ll << HS_MAX_QUBITS)) return dfail(HS_EINVAL, "N must be in [1, 2^30]");
     if (n_diags < 1 || n_diags > 65535 || !offsets || !host_diags) return dfail(HS_EINVAL, "bad diagonals");
     std::vector<int64_t> offs(offsets, offsets + n_diags);
     for (int j = 0; j < n_diags; ++j) {

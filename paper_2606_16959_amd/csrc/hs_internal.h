@@ -82,6 +82,7 @@ struct TileArgs {
     int32_t swizzle;         // deal contiguous eighths of the tiles to the 8 XCDs
     const void *x0;          // Horner launches: y = x0 + alpha (A x), x0 read at the row only
     double alpha_re, alpha_im;
+    int32_t ragged;          // open contiguous launch whose last tile passes row N (any N)
 };
 
 struct ConstructArgs {

@@ -195,14 +195,15 @@ __device__ __forceinline__ C2<R> cmask(C2<R> c, bool keep) {
 
 // Coefficients of one diagonal for every row pair a thread owns (masked
 // loads: invalid rows read entry 0 and are zeroed when consumed).
-template <typename R, int P, int NT>
+template <typename R, int P, int NT, bool SINGLE = false>
 __device__ __forceinline__ void load_diag(C2<R> (&c)[P][2], const DiagDesc &dd, int tid, int T,
                                           int base, int qb, int logW) {
     const C2<R> *cp = reinterpret_cast<const C2<R> *>(dd.ptr);
     const int neg = dd.off < 0 ? dd.off : 0;
     const int len = dd.hi - dd.lo;            // N - |d| entries
     const int W = 1 << logW;
-    if ((dd.off & 1) == 0) {
+    // SINGLE: entry-wise loads (a diagonal of odd length ends inside a pair)
+    if (!SINGLE && (dd.off & 1) == 0) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const int i0 = 2 * tid + 2 * NT * p;
@@ -228,7 +229,9 @@ __device__ __forceinline__ void load_diag(C2<R> (&c)[P][2], const DiagDesc &dd, 
 
 // HORNER (open launches only): the output row is x0[r] + alpha * (A x)[r],
 // one Horner stage of a polynomial in A applied to a state.
-template <typename R, int B, int RPT, bool CLOSED, bool HORNER = false, int NT = kTileThreads>
+// RAG (open contiguous launches only): N need not be a multiple of the tile;
+// rows at or past N are neither loaded nor stored.
+template <typename R, int B, int RPT, bool CLOSED, bool HORNER = false, int NT = kTileThreads, bool RAG = false>
 __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
     static_assert(RPT % 2 == 0, "rows come in pairs");
     constexpr int P = RPT / 2;
@@ -267,8 +270,15 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
             const int r0 = i0 < T ? row_of(i0) : base;
 #pragma unroll
             for (int b = 0; b < B; ++b) {
-                if (CLOSED) ld2(x + b * a.stride, r0, u[p][0][b], u[p][1][b]);
-                else ld2_cached(x + b * a.stride, r0, u[p][0][b], u[p][1][b]);
+                if (RAG) {
+                    const C2<R> z{(R)0, (R)0};
+                    u[p][0][b] = r0 < a.N ? x[b * a.stride + r0] : z;
+                    u[p][1][b] = r0 + 1 < a.N ? x[b * a.stride + r0 + 1] : z;
+                } else if (CLOSED) {
+                    ld2(x + b * a.stride, r0, u[p][0][b], u[p][1][b]);
+                } else {
+                    ld2_cached(x + b * a.stride, r0, u[p][0][b], u[p][1][b]);
+                }
             }
         }
 #pragma unroll
@@ -285,7 +295,7 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
 
     const int total = a.dstart[a.nf];
     C2<R> c[P][2];
-    load_diag<R, P, NT>(c, a.desc[0], tid, T, base, qb, logW);
+    load_diag<R, P, NT, RAG>(c, a.desc[0], tid, T, base, qb, logW);
     __syncthreads();
 
     C2<R> acc[P][2][B];
@@ -302,7 +312,7 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
         for (; dj < a.dstart[f + 1]; ++dj) {
             const DiagDesc dd = a.desc[dj];
             C2<R> cn[P][2];
-            if (HS_TILE_PREFETCH && dj + 1 < total) load_diag<R, P, NT>(cn, a.desc[dj + 1], tid, T, base, qb, logW);
+            if (HS_TILE_PREFETCH && dj + 1 < total) load_diag<R, P, NT, RAG>(cn, a.desc[dj + 1], tid, T, base, qb, logW);
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int i0 = 2 * tid + 2 * NT * p;
@@ -342,7 +352,7 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
                 }
             }
             if (!HS_TILE_PREFETCH && dj + 1 < total) {
-                load_diag<R, P, NT>(c, a.desc[dj + 1], tid, T, base, qb, logW);
+                load_diag<R, P, NT, RAG>(c, a.desc[dj + 1], tid, T, base, qb, logW);
             } else {
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
@@ -377,7 +387,13 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
 #pragma unroll
             for (int b = 0; b < B; ++b) {
                 C2<R> v0, v1;
-                ld2(x0 + b * a.stride, r0, v0, v1);
+                if (RAG) {
+                    const C2<R> z{(R)0, (R)0};
+                    v0 = r0 < a.N ? x0[b * a.stride + r0] : z;
+                    v1 = r0 + 1 < a.N ? x0[b * a.stride + r0 + 1] : z;
+                } else {
+                    ld2(x0 + b * a.stride, r0, v0, v1);
+                }
                 cfma(v0, al, acc[p][0][b]);
                 cfma(v1, al, acc[p][1][b]);
                 acc[p][0][b] = v0;
@@ -392,8 +408,8 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
             const int r0 = row_of(i0);
 #pragma unroll
             for (int b = 0; b < B; ++b) {
-                y[b * a.stride + r0] = acc[p][0][b];
-                y[b * a.stride + r0 + 1] = acc[p][1][b];
+                if (!RAG || r0 < a.N) y[b * a.stride + r0] = acc[p][0][b];
+                if (!RAG || r0 + 1 < a.N) y[b * a.stride + r0 + 1] = acc[p][1][b];
             }
         }
     }
@@ -529,13 +545,13 @@ static std::mutex &lds_attr_mutex() {
 // Launch with the smallest rows-per-thread instantiation (power of two, down
 // to one row pair) that still gives every tile row a thread: a tile smaller
 // than the kernel's capacity would otherwise issue masked loads and FMAs.
-template <typename R, int B, int RPT, bool CLOSED, bool HORNER, int NT>
+template <typename R, int B, int RPT, bool CLOSED, bool HORNER, int NT, bool RAG = false>
 static int tile_launch(const TileArgs &a, int rows_per_thread, size_t lds, int grid, void *stream) {
     if constexpr (RPT > 2) {
         if (rows_per_thread <= RPT / 2)
-            return tile_launch<R, B, RPT / 2, CLOSED, HORNER, NT>(a, rows_per_thread, lds, grid, stream);
+            return tile_launch<R, B, RPT / 2, CLOSED, HORNER, NT, RAG>(a, rows_per_thread, lds, grid, stream);
     }
-    auto kern = dia_tile_kernel<R, B, RPT, CLOSED, HORNER, NT>;
+    auto kern = dia_tile_kernel<R, B, RPT, CLOSED, HORNER, NT, RAG>;
     if (lds > 65536) {
         // allow this instantiation the dynamic LDS the launch needs (raised
         // only when a larger launch arrives; the planner keeps lds within the
@@ -565,16 +581,23 @@ static int tile_dispatch_b(const TileArgs &a, int mode, void *stream) {
     constexpr int NTC = tile_threads(c128, B);
     constexpr int NTO = tile_threads(c128, B, true);
     const size_t lds = (size_t)a.T * B * sizeof(C2<R>);
-    const int grid = (int)(a.N / a.T);
-    // every tile row must belong to a thread, and the tile must fit the LDS budget
+    // every tile row must belong to a thread, and the tile must fit the LDS
+    // budget; only open contiguous launches may end in a partial tile
     const int nt = mode == kClosed ? NTC : NTO;
     const int rpt = mode == kClosed ? RPT : RPT_OPEN;
-    if (a.T < 2 || a.T > nt * rpt || lds > (size_t)HS_TILE_LDS_BYTES || a.N % a.T)
+    if (a.T < 2 || a.T > nt * rpt || lds > (size_t)HS_TILE_LDS_BYTES) return (int)hipErrorInvalidValue;
+    const bool rag = a.ragged != 0;
+    if ((a.N % a.T != 0) != rag) return (int)hipErrorInvalidValue;
+    if (rag && (mode == kClosed || a.qb != 0 || a.logW != 0 || a.nlw_log != 0 || a.swizzle))
         return (int)hipErrorInvalidValue;
+    const int grid = (int)((a.N + a.T - 1) / a.T);
     const int need = (a.T + nt - 1) / nt;
     if (mode == kClosed) return tile_launch<R, B, RPT, true, false, NTC>(a, need, lds, grid, stream);
-    if (mode == kOpen) return tile_launch<R, B, RPT_OPEN, false, false, NTO>(a, need, lds, grid, stream);
-    return tile_launch<R, B, RPT_OPEN, false, true, NTO>(a, need, lds, grid, stream);
+    if (mode == kOpen)
+        return rag ? tile_launch<R, B, RPT_OPEN, false, false, NTO, true>(a, need, lds, grid, stream)
+                   : tile_launch<R, B, RPT_OPEN, false, false, NTO>(a, need, lds, grid, stream);
+    return rag ? tile_launch<R, B, RPT_OPEN, false, true, NTO, true>(a, need, lds, grid, stream)
+               : tile_launch<R, B, RPT_OPEN, false, true, NTO>(a, need, lds, grid, stream);
 }
 
 template <typename R>

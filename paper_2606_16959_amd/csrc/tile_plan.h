@@ -113,6 +113,17 @@ inline Geo generic_geometry(const long long *offsets, int nd, long long N, int d
     const PlanKey key = plan_key(chunk, true);
     const int q = orall ? __builtin_ctzll(orall) : 0;
     Geo geo = geometry(0, 0, n, Tmax);
+    if (N < 2 || (N & (N - 1))) {
+        // N not a power of two (or 1): contiguous tiles of the smallest power
+        // of two >= N (at least one row pair, at most Tmax); the last tile is partial
+        int lt = 1;
+        while ((1ll << lt) < N && (2ll << lt) <= Tmax) ++lt;
+        geo = Geo{};
+        geo.kb = lt;
+        geo.T = 1 << lt;
+        geo.ok = true;
+        return geo;
+    }
     if (orall && (1 << std::min(q, 20)) >= w_min(dtype, key) && maxabs >= Tmax) {
         const int need = ilog2(maxabs >> q) + 1;     // levels reaching the farthest offset
         const int logT = std::min(ilog2(Tmax), n);
@@ -156,6 +167,7 @@ inline TileArgs open_args(const Geo &geo, const DiagDesc *ddev, int nd, const vo
     a.nrm2 = nullptr;
     a.viol = nullptr;
     a.swizzle = 0;
+    a.ragged = (N % geo.T) != 0;
     return a;
 }
 

@@ -93,6 +93,9 @@ def _random_dia(rng, N, offsets, dtype):
     (2, 1, "c128", "all"), (1 << 10, 1, "c128", "near"), (1 << 14, 3, "c64", "near"),
     (1 << 16, 1, "c64", "far"), (1 << 16, 8, "c64", "far"), (1 << 15, 2, "c128", "strided"),
     (1 << 16, 1, "c64", "strided"), (1 << 13, 5, "c128", "mixed"), (1 << 12, 11, "c64", "mixed"),
+    # N not a multiple of the tile (any N): the last tile is partial, odd N makes odd diagonals
+    (1, 1, "c128", "all"), (3, 2, "c64", "all"), (1000, 3, "c64", "near"), (4097, 1, "c128", "far"),
+    (12345, 2, "c64", "mixed"), (99999, 5, "c64", "far"),
 ])
 def test_dia_spmv_matches_definition(N, B, dtype, kind):
     hs, torch = hs_gpu()

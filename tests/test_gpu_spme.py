@@ -183,3 +183,50 @@ def test_single_propagator_full_size_sampled_rows():
     terms = opauli.parse_terms(Hw.strings, Hw.coeffs, n)
     ref = otay.step_rows(terms, x0.astype(np.complex128), rows, 1.0 / r, 1)
     assert np.abs(got[rows].astype(np.complex128) - ref).max() <= 2.0 ** -20 * np.abs(x0).max() * 4
+
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_ragged_operator_pipeline(dtype):
+    """An operator of N = 777 rows (not a power of two, odd): a random
+    Hermitian DIA matrix through SpME (with squaring), the Alg. 3 loop and the
+    fused Taylor update, against the oracle's sparse products."""
+    hd, torch = _dia()
+    from oracle import taylor as otay
+    import scipy.sparse as sp
+    N = 777
+    rng = np.random.default_rng(777)
+    D = {0: rng.normal(size=N) + 0j}
+    for d in (1, 2, 37, 400):
+        v = 0.3 * (rng.normal(size=N - d) + 1j * rng.normal(size=N - d))
+        D[d], D[-d] = v, np.conj(v)
+    note(f"ragged operator N=777 {dtype}")
+    H = hd.from_dict(D, N)
+    Href = sp.csr_matrix(odia.dia_to_dense(D, N))
+    dt = 0.07
+    U, K = hd.spme(H, dt)
+    Uref, Kref, offs = ospme.spme(Href, dt)
+    assert K == Kref and U.offsets == offs
+    assert np.abs(odia.dia_to_dense(U.to_dict(), N) - Uref.toarray()).max() <= 1e-12
+    npd = np.complex128 if dtype == "c128" else np.complex64
+    psi0 = (rng.normal(size=(3, N)) + 1j * rng.normal(size=(3, N)))
+    psi0 /= np.linalg.norm(psi0, axis=1, keepdims=True)
+    tol = 1e-12 if dtype == "c128" else 2e-6
+    # Alg. 3 loop: psi <- U^5 psi
+    Ud = U if dtype == "c128" else U.to_c64()
+    psi = torch.from_numpy(psi0.astype(npd)).cuda()
+    hd.evolve(Ud, psi, 5)
+    ref = psi0.astype(npd).astype(np.complex128)
+    for _ in range(5):
+        ref = (Uref @ ref.T).T
+    assert np.abs(psi.cpu().numpy() - ref).max() <= tol
+    # fused Taylor update: p_K(-i dt H)^4 psi
+    Hd = H if dtype == "c128" else H.to_c64()
+    K2 = hd.taylor_terms(H, dt)
+    assert K2 == otay.taylor_terms(Href, dt)
+    psi = torch.from_numpy(psi0.astype(npd)).cuda()
+    hd.taylor_evolve(Hd, psi, dt, K2, 4)
+    ref = otay.taylor_evolve(Href, psi0.astype(npd).astype(np.complex128), dt, K2, 4)
+    assert np.abs(psi.cpu().numpy() - ref).max() <= tol
+    for X in {id(v): v for v in (H, U, Ud, Hd)}.values():
+        X.close()
