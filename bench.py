@@ -191,7 +191,7 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, command):
     tile = [r for r in trace if "dia_tile_kernel" in r["Kernel_Name"]]
     os.makedirs(OUT_DIR, exist_ok=True)
     md = ["# dia_tile_kernel on tfim2d 5x5 + ancilla, n=26, complex64, budget 16", "",
-          "Command (repository root, GPU box):", "", "```", command, "```", "",
+          "Command (repository root, on the MI355X):", "", "```", command, "```", "",
           "## rocprofv3 --kernel-trace --stats summary", "",
           "| kernel | calls | avg us | min us | max us | % |", "|---|---|---|---|---|---|"]
     for r in stats:
@@ -253,8 +253,8 @@ def sweep(torch, steps, warmup, rounds=3):
     library; one handle keeps a plan per setting), timed in interleaved rounds
     (median); writes a summary under profiles/."""
     import paper_2606_16959_amd as hs
-    from workloads import config_hamiltonian, states as ws
-    H = config_hamiltonian(3)
+    from workloads import workload_hamiltonian, states as ws
+    H = workload_hamiltonian("tfim_5x5_ancilla_n26")
     N = 1 << H.n
     psi0 = ws.random_phase_state(H.n, 3, np.complex64)
     f = hs.build_factors(H.strings, H.coeffs, H.n, 1.0, 50, 16, dtype="c64")
@@ -302,7 +302,7 @@ def sweep(torch, steps, warmup, rounds=3):
                 ref = out if ref is None else ref
         log(f"sweep round {rnd} done")
     md = ["# Launch-plan sweep: dia_tile_kernel, tfim2d 5x5 + ancilla, n=26, complex64", "",
-          "Command (repository root, GPU box): `python3 bench.py --sweep`", "",
+          "Command (repository root, on the MI355X): `python3 bench.py --sweep`", "",
           f"Per variant: {warmup} warm-up + {steps} timed steps, repeated in {rounds} interleaved "
           "rounds; median ms/step. Every variant's state after the first round is compared bit for "
           "bit with the first variant's.", "",
@@ -320,31 +320,33 @@ def sweep(torch, steps, warmup, rounds=3):
     print("\n".join(md))
 
 
-ACCURACY_STEPS = {1: 10, 2: 100, 4: 2}      # whole runs for configs 1 and 2; 2 steps at n = 24, B = 8
+# steps checked against the oracle: whole runs for the n = 8 and n = 20 chains, 2 at n = 24 (8 states)
+ACCURACY_STEPS = {"tfim_chain_n8": 10, "heisenberg_chain_n20": 100, "maxcut_3reg_n24": 2}
 
 
-def other_configs(torch, steps=10, warmup=2):
-    """The other workload configurations in the same harness: per-step time
+def other_workloads(torch, steps=10, warmup=2):
+    """The other named workloads in the same harness: per-step time
     and algorithmic GB/s (n <= 20 states stay in the 256 MB last-level cache,
     so only n = 24 and n = 26 figures are HBM-bound)."""
     import paper_2606_16959_amd as hs
-    from workloads import config_hamiltonian, states as ws
-    from workloads.hamiltonians import CONFIG_RUN
+    from workloads import workload_hamiltonian, states as ws
+    from workloads.hamiltonians import WORKLOAD_RUN
     from oracle import evolve as oev, factors as ofac, pauli as opauli
     out = []
     oracle_refs, c128_states = {}, {}
-    cases = [(1, "c128", False), (2, "c128", False), (2, "c64", False), (4, "c64", False),
-             (3, "c64", True)]
+    cases = [("tfim_chain_n8", "c128", False), ("heisenberg_chain_n20", "c128", False),
+             ("heisenberg_chain_n20", "c64", False), ("maxcut_3reg_n24", "c64", False),
+             ("tfim_5x5_ancilla_n26", "c64", True)]
     for cfg, dtype, renorm in cases:
-        H = config_hamiltonian(cfg)
-        run = CONFIG_RUN[cfg]
+        H = workload_hamiltonian(cfg)
+        run = WORKLOAD_RUN[cfg]
         npd = np.complex128 if dtype == "c128" else np.complex64
         elem = 16 if dtype == "c128" else 8
         f = hs.build_factors(H.strings, H.coeffs, H.n, run["t"], run["steps"], run["budget"], dtype=dtype)
         B = run["batch"]
         launches = f.step_launches(B)
         per = launch_bytes(f.describe(), launches, 1 << H.n, B, elem)
-        psi = torch.from_numpy(np.ascontiguousarray(ws.config_states(cfg, npd))).cuda()
+        psi = torch.from_numpy(np.ascontiguousarray(ws.workload_states(cfg, npd))).cuda()
         for _ in range(warmup):
             hs.evolve(f, psi, 1, renorm=renorm)
         torch.cuda.synchronize()
@@ -355,16 +357,16 @@ def other_configs(torch, steps=10, warmup=2):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
-        row = {"config": cfg, "n": H.n, "batch": B, "dtype": dtype, "renorm": renorm,
+        row = {"workload": cfg, "n": H.n, "batch": B, "dtype": dtype, "renorm": renorm,
                "launches_per_step": len(launches), "ms_per_step": round(ms, 4),
                "gb_per_step": round(sum(per) / 1e9, 3), "gbs": round(sum(per) / ms / 1e6, 1)}
         if B > 1:
             row["ms_per_state_step"] = round(ms / B, 4)
         if cfg in ACCURACY_STEPS:
             # error against the FP64 oracle over the first k steps from the
-            # configuration's initial states (complex64 also against complex128)
+            # workload's initial states (complex64 also against complex128)
             k = ACCURACY_STEPS[cfg]
-            psi0 = np.ascontiguousarray(ws.config_states(cfg, np.complex128))
+            psi0 = np.ascontiguousarray(ws.workload_states(cfg, np.complex128))
             if cfg not in oracle_refs:
                 terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
                 part = ofac.first_fit(terms, run["budget"], run["t"] / run["steps"])
@@ -379,7 +381,7 @@ def other_configs(torch, steps=10, warmup=2):
                 row["fidelity_vs_c128_gpu"] = accuracy(got, c128_states[cfg])["min_fidelity"]
             del pa
         out.append(row)
-        log(f"config {cfg} {dtype} B={B} renorm={renorm}: {ms:.4f} ms/step {row['gbs']} GB/s")
+        log(f"{cfg} {dtype} B={B} renorm={renorm}: {ms:.4f} ms/step {row['gbs']} GB/s")
         f.close()
         del psi
         torch.cuda.empty_cache()
@@ -393,10 +395,10 @@ def higher_order_leg(torch, steps=10, warmup=3):
     launch's coefficient diagonals plus the state read and written, summed
     over the first, middle and last steps' launch lists."""
     import paper_2606_16959_amd as hs
-    from workloads import config_hamiltonian, states as ws
-    from workloads.hamiltonians import CONFIG_RUN
-    H = config_hamiltonian(3)
-    run = CONFIG_RUN[3]
+    from workloads import workload_hamiltonian, states as ws
+    from workloads.hamiltonians import WORKLOAD_RUN
+    H = workload_hamiltonian("tfim_5x5_ancilla_n26")
+    run = WORKLOAD_RUN["tfim_5x5_ancilla_n26"]
     N = 1 << H.n
     out = []
     for order in (2, 4):
@@ -407,7 +409,7 @@ def higher_order_leg(torch, steps=10, warmup=3):
                  for p in (1, 2, 3)}
         nbytes = sum(parts[1]) + (steps - 2) * sum(parts[2]) + sum(parts[3])
         n_launch = len(parts[1]) + (steps - 2) * len(parts[2]) + len(parts[3])
-        psi = torch.from_numpy(np.ascontiguousarray(ws.config_states(3, np.complex64))).cuda()
+        psi = torch.from_numpy(np.ascontiguousarray(ws.workload_states("tfim_5x5_ancilla_n26", np.complex64))).cuda()
         hs.evolve(f, psi, warmup)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -440,9 +442,9 @@ def taylor_leg(torch, cases=None, timed_steps=3):
     diagonal of H once, plus the state read (partners), the step's input read
     (epilogue) and the output written."""
     import paper_2606_16959_amd.dia as hd
-    from workloads import config_hamiltonian, hamiltonians as wh, states as ws
+    from workloads import workload_hamiltonian, hamiltonians as wh, states as ws
     cases = cases or [("tfim1d_n24_h1_t1", lambda: wh.tfim_1d(24, 1.0, 1.0)),
-                      ("tfim2d_5x5_plus1_n26_t1", lambda: config_hamiltonian(3))]
+                      ("tfim2d_5x5_plus1_n26_t1", lambda: workload_hamiltonian("tfim_5x5_ancilla_n26"))]
     out = []
     for name, make in cases:
         Hw = make()
@@ -483,7 +485,7 @@ def taylor_leg(torch, cases=None, timed_steps=3):
 
 def write_serve_summary(stats, command, fname):
     md = ["# Served stream: mixed TFIM / Heisenberg / MaxCut / TSP jobs, n in [10, 24], complex64", "",
-          f"Command (repository root, GPU box): `{command}`", "",
+          f"Command (repository root, on the MI355X): `{command}`", "",
           "Latency = arrival -> completion event of the job's last kernel; queue wait = arrival -> "
           "admission; service = admission -> completion (factor build + state setup + evolution). "
           "Oracle check: jobs hashed into a 5% sample with n <= 16, state column 0, FP64 oracle.", "",
@@ -558,9 +560,9 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-oracle-nmax", type=int, default=16)
     ap.add_argument("--serve-only", action="store_true", help="only the served stream")
-    ap.add_argument("--leg", choices=["taylor", "higher_order", "single_propagator", "other_configs"],
+    ap.add_argument("--leg", choices=["taylor", "higher_order", "single_propagator", "other_workloads"],
                     help="run one secondary leg alone and print its JSON (for profiling)")
-    ap.add_argument("--no-other-configs", action="store_true")
+    ap.add_argument("--no-other-workloads", action="store_true")
     ap.add_argument("--serve-sweep", default="", help="comma-separated arrival rates (jobs/s)")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
                     help="write profiles/ summaries from rocprofv3 output directories")
@@ -581,7 +583,7 @@ def main():
 
     import torch
     import paper_2606_16959_amd as hs
-    from workloads import config_hamiltonian, states as ws
+    from workloads import workload_hamiltonian, states as ws
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
@@ -590,7 +592,7 @@ def main():
         return
     if args.leg:
         legs = {"taylor": taylor_leg, "higher_order": higher_order_leg,
-                "single_propagator": single_propagator_leg, "other_configs": other_configs}
+                "single_propagator": single_propagator_leg, "other_workloads": other_workloads}
         print(json.dumps({"leg": args.leg, "result": legs[args.leg](torch)}), flush=True)
         return
     if args.serve_only:
@@ -608,7 +610,7 @@ def main():
                                  f"{args.serve_jobs} --serve-slots {args.serve_slots}",
                             f"serve_rate_sweep_{args.serve_jobs}jobs.md")
         return
-    H = config_hamiltonian(3)
+    H = workload_hamiltonian("tfim_5x5_ancilla_n26")
     N = 1 << H.n
     budget, t, steps_total = 16, 1.0, 50
 
@@ -680,10 +682,10 @@ def main():
         del pa, ref
 
     others = None
-    if not args.no_other_configs:
+    if not args.no_other_workloads:
         f.close()
         torch.cuda.empty_cache()
-        others = other_configs(torch)
+        others = other_workloads(torch)
         others.append({"higher_order": higher_order_leg(torch)})
         others.append({"taylor_fused": taylor_leg(torch)})
         others.append({"single_propagator": single_propagator_leg(torch)})
@@ -704,7 +706,7 @@ def main():
         "step_ms_median": round(float(np.median(step_ms)), 4),
         "step_ms_p90": round(float(np.percentile(step_ms, 90)), 4),
         "bytes_per_step": int(step_bytes), "build_s": round(build_s, 3),
-        "closure_ok": bool(closure_ok), **extra, "other_configs": others, "serve": serve,
+        "closure_ok": bool(closure_ok), **extra, "other_workloads": others, "serve": serve,
     }
     print(json.dumps(line), flush=True)
     f.close()

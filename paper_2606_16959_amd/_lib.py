@@ -77,8 +77,7 @@ def load():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
-                              "(python -m paper_2606_16959_amd.build)")
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2606_16959_amd.build")
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIG.items():
             fn = getattr(lib, name)

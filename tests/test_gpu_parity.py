@@ -12,7 +12,7 @@ import pytest
 
 from gpu_common import fid, hs_gpu, note, oracle_run, oracle_threads, tol_c64
 from oracle import dia as odia, factors as ofac, metrics, pauli as opauli
-from workloads import config_hamiltonian, hamiltonians as wh, states as ws
+from workloads import workload_hamiltonian, hamiltonians as wh, states as ws
 
 pytestmark = pytest.mark.gpu
 
@@ -28,12 +28,12 @@ def _heis10():
 # ------------------------------------------------------------------ (a0) construction
 
 @pytest.mark.parametrize("case,dtype,merge", [
-    ("cfg1", "c128", True), ("cfg1", "c64", True), ("heis10", "c128", False), ("heis10", "c64", True),
+    ("tfim8", "c128", True), ("tfim8", "c64", True), ("heis10", "c128", False), ("heis10", "c64", True),
 ])
 def test_construction_matches_oracle_entries(case, dtype, merge):
     hs, torch = hs_gpu()
-    if case == "cfg1":
-        H, budget, t, steps = config_hamiltonian(1), 8, 1.0, 10
+    if case == "tfim8":
+        H, budget, t, steps = workload_hamiltonian("tfim_chain_n8"), 8, 1.0, 10
     else:
         H, budget, t, steps = _heis10(), 16, 0.7, 9
     note(f"construct {case} {dtype} merge={merge}")
@@ -56,10 +56,10 @@ def test_construction_matches_oracle_entries(case, dtype, merge):
     f.close()
 
 
-def test_construction_sampled_at_full_size_config3():
+def test_construction_sampled_at_full_size_tfim_5x5_n26():
     hs, torch = hs_gpu()
-    H = config_hamiltonian(3)
-    note("construct config3 n=26 c64 (sampled windows)")
+    H = workload_hamiltonian("tfim_5x5_ancilla_n26")
+    note("construct tfim_5x5_ancilla_n26 c64 (sampled windows)")
     f = hs.build_factors(H.strings, H.coeffs, H.n, 1.0, 50, 16, dtype="c64")
     terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
     part = ofac.first_fit(terms, 16, 1.0 / 50)
@@ -149,18 +149,18 @@ def _evolve_vs_oracle(H, budget, t, steps, psi0, dtype, run_steps=None, **kw):
     return got, ref
 
 
-def test_evolve_config1_complex128():
-    note("evolve config1 c128")
-    H = config_hamiltonian(1)
+def test_evolve_tfim_chain_n8_complex128():
+    note("evolve tfim_chain_n8 c128")
+    H = workload_hamiltonian("tfim_chain_n8")
     got, ref = _evolve_vs_oracle(H, 8, 1.0, 10, ws.zero_state(8), "c128")
     assert np.abs(got - ref).max() <= 1e-12
     assert fid(got, ref)[0] >= 1 - 1e-12
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_evolve_config2(dtype):
-    note(f"evolve config2 {dtype}")
-    H = config_hamiltonian(2)
+def test_evolve_heisenberg_chain_n20(dtype):
+    note(f"evolve heisenberg_chain_n20 {dtype}")
+    H = workload_hamiltonian("heisenberg_chain_n20")
     got, ref = _evolve_vs_oracle(H, 16, 2.0, 100, ws.neel_state(20), dtype)
     F = fid(got, ref)[0]
     if dtype == "c128":
@@ -169,9 +169,9 @@ def test_evolve_config2(dtype):
         assert F >= 1 - 1e-6
 
 
-def test_evolve_config3_full_size_few_steps():
-    note("evolve config3 n=26 c64, 2 of 50 steps, vs oracle")
-    H = config_hamiltonian(3)
+def test_evolve_tfim_5x5_n26_full_size_few_steps():
+    note("evolve tfim_5x5_ancilla_n26 c64, 2 of 50 steps, vs oracle")
+    H = workload_hamiltonian("tfim_5x5_ancilla_n26")
     psi0 = ws.random_phase_state(26, 3, np.complex64)
     got, ref = _evolve_vs_oracle(H, 16, 1.0, 50, psi0, "c64", run_steps=2)
     assert fid(got, ref)[0] >= 1 - 1e-6
@@ -179,11 +179,11 @@ def test_evolve_config3_full_size_few_steps():
     assert np.abs(got - ref).max() <= bound
 
 
-def test_evolve_config4_full_size_batched():
+def test_evolve_maxcut_n24_full_size_batched():
     hs, torch = hs_gpu()
-    note("evolve config4 n=24 B=8 c64, 2 of 200 steps, vs oracle + column invariance")
-    H = config_hamiltonian(4)
-    psi0 = ws.config_states(4, np.complex64)
+    note("evolve maxcut_3reg_n24 B=8 c64, 2 of 200 steps, vs oracle + column invariance")
+    H = workload_hamiltonian("maxcut_3reg_n24")
+    psi0 = ws.workload_states("maxcut_3reg_n24", np.complex64)
     got, ref = _evolve_vs_oracle(H, 16, 1.0, 200, psi0, "c64", run_steps=2)
     assert np.all(fid(got, ref) >= 1 - 1e-6)
     # column b of the batched run equals the single-state run, bit for bit
@@ -197,8 +197,8 @@ def test_evolve_config4_full_size_batched():
 
 def test_fused_unfused_split_and_repeat_are_bitwise_equal():
     hs, torch = hs_gpu()
-    H = config_hamiltonian(2)
-    note("bitwise: fused/unfused/split/repeat config2 c64")
+    H = workload_hamiltonian("heisenberg_chain_n20")
+    note("bitwise: fused/unfused/split/repeat heisenberg_chain_n20 c64")
     f = hs.build_factors(H.strings, H.coeffs, 20, 2.0, 100, 16, dtype="c64")
     psi0 = _to_dev(torch, ws.neel_state(20, np.complex64)[None], np.complex64)
     runs = []
@@ -220,8 +220,8 @@ def test_fused_unfused_split_and_repeat_are_bitwise_equal():
 
 def test_renorm_keeps_unit_norm_and_fidelity():
     hs, torch = hs_gpu()
-    H = config_hamiltonian(2)
-    note("renorm config2 c64")
+    H = workload_hamiltonian("heisenberg_chain_n20")
+    note("renorm heisenberg_chain_n20 c64")
     f = hs.build_factors(H.strings, H.coeffs, 20, 2.0, 100, 16, dtype="c64")
     psi0 = ws.neel_state(20, np.complex64)[None]
     p = _to_dev(torch, psi0, np.complex64)
@@ -325,8 +325,8 @@ def test_degenerate_cases():
 
 def test_merge_flag_does_not_change_the_result():
     hs, torch = hs_gpu()
-    note("merge on/off config1 c128")
-    H = config_hamiltonian(1)
+    note("merge on/off tfim_chain_n8 c128")
+    H = workload_hamiltonian("tfim_chain_n8")
     outs = []
     for merge in (True, False):
         f = hs.build_factors(H.strings, H.coeffs, 8, 1.0, 10, 8, dtype="c128", merge_diag=merge)
@@ -343,8 +343,8 @@ def test_merge_flag_does_not_change_the_result():
 def test_higher_order_products_match_oracle(order):
     hs, torch = hs_gpu()
     from oracle import evolve as oev
-    note(f"order {order}: config1 c128 and config2 c64")
-    H = config_hamiltonian(1)
+    note(f"order {order}: tfim_chain_n8 c128 and heisenberg_chain_n20 c64")
+    H = workload_hamiltonian("tfim_chain_n8")
     terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
     part = ofac.first_fit(terms, 8, 0.1)
     f = hs.build_factors(H.strings, H.coeffs, 8, 1.0, 10, 8, dtype="c128", order=order)
@@ -360,7 +360,7 @@ def test_higher_order_products_match_oracle(order):
     hs.evolve(f, q, 10, fuse=False)
     assert np.array_equal(p.cpu().numpy(), q.cpu().numpy())
     f.close()
-    H = config_hamiltonian(2)
+    H = workload_hamiltonian("heisenberg_chain_n20")
     terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
     part = ofac.first_fit(terms, 16, 0.02)
     f = hs.build_factors(H.strings, H.coeffs, 20, 2.0, 100, 16, dtype="c64", order=order)
@@ -413,14 +413,14 @@ def test_long_range_factor_takes_an_open_launch(n, dtype):
 
 
 @pytest.mark.parametrize("order", [2, 4])
-def test_higher_order_full_size_config3(order):
+def test_higher_order_full_size_tfim_5x5_n26(order):
     """The n = 26 workload with the bench's launch plan, 3 steps (first,
     middle and last step lists, joint factors included), against the
     oracle's unmerged product on the full state."""
     hs, torch = hs_gpu()
     from oracle import evolve as oev
-    note(f"order {order}: config3 n=26 c64, 3 of 50 steps, vs oracle")
-    H = config_hamiltonian(3)
+    note(f"order {order}: tfim_5x5_ancilla_n26 c64, 3 of 50 steps, vs oracle")
+    H = workload_hamiltonian("tfim_5x5_ancilla_n26")
     psi0 = ws.random_phase_state(26, 3, np.complex64)
     f = hs.build_factors(H.strings, H.coeffs, 26, 1.0, 50, 16, dtype="c64", order=order)
     desc = f.describe()
@@ -441,15 +441,15 @@ def test_higher_order_full_size_config3(order):
     assert np.abs(got - ref).max() <= applications * 2.0 ** -22 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("cfg,steps", [(2, 100), (4, 5)])
+@pytest.mark.parametrize("cfg,steps", [("heisenberg_chain_n20", 100), ("maxcut_3reg_n24", 5)])
 def test_complex64_matches_the_complex128_path(cfg, steps):
     """The complex64 path against the plain complex128 GPU path on the same
-    inputs (config 2: the whole run; config 4: 8 batched states)."""
+    inputs (the n = 20 chain: the whole run; n = 24 MaxCut: 8 batched states)."""
     hs, torch = hs_gpu()
-    H = config_hamiltonian(cfg)
-    run = wh.CONFIG_RUN[cfg]
-    psi0 = np.ascontiguousarray(ws.config_states(cfg, np.complex128))
-    note(f"config {cfg}: complex64 vs complex128, {steps} steps")
+    H = workload_hamiltonian(cfg)
+    run = wh.WORKLOAD_RUN[cfg]
+    psi0 = np.ascontiguousarray(ws.workload_states(cfg, np.complex128))
+    note(f"{cfg}: complex64 vs complex128, {steps} steps")
     out = {}
     for dtype, npd in (("c128", np.complex128), ("c64", np.complex64)):
         f = hs.build_factors(H.strings, H.coeffs, H.n, run["t"], run["steps"], run["budget"], dtype=dtype)

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import factors as ofac, pauli as opauli
-from workloads import config_hamiltonian, hamiltonians as wh
+from workloads import workload_hamiltonian, hamiltonians as wh
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -64,10 +64,10 @@ def _check_plan_matches_oracle(hs, H, budget, t, steps, merge=True):
     f.close()
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
-def test_plan_matches_oracle_on_configs(hs, cfg):
-    H = config_hamiltonian(cfg)
-    run = wh.CONFIG_RUN[cfg]
+@pytest.mark.parametrize("cfg", list(wh.WORKLOADS))
+def test_plan_matches_oracle_on_workloads(hs, cfg):
+    H = workload_hamiltonian(cfg)
+    run = wh.WORKLOAD_RUN[cfg]
     _check_plan_matches_oracle(hs, H, run["budget"], run["t"], run["steps"])
 
 
@@ -130,7 +130,7 @@ def test_planned_handle_cannot_evolve(hs):
 
 
 def test_footprint_counts_diagonals_states_and_workspace(hs):
-    H = config_hamiltonian(3)
+    H = workload_hamiltonian("tfim_5x5_ancilla_n26")
     f = hs.plan(H.strings, H.coeffs, H.n, 1.0, 50, 16)
     desc = f.describe()
     diag_bytes = sum(x["bytes"] for x in desc["factors"])
@@ -142,11 +142,11 @@ def test_footprint_counts_diagonals_states_and_workspace(hs):
 
 
 @pytest.mark.parametrize("order", [2, 4])
-@pytest.mark.parametrize("cfg", [1, 2, 3])
+@pytest.mark.parametrize("cfg", list(wh.WORKLOADS[:3]))
 def test_higher_order_plan_matches_oracle_sequence(hs, cfg, order):
     from oracle import evolve as oev
-    H = config_hamiltonian(cfg)
-    run = wh.CONFIG_RUN[cfg]
+    H = workload_hamiltonian(cfg)
+    run = wh.WORKLOAD_RUN[cfg]
     dt = run["t"] / run["steps"]
     f = hs.plan(H.strings, H.coeffs, H.n, run["t"], run["steps"], run["budget"], order=order)
     desc = f.describe()
@@ -178,7 +178,7 @@ def test_higher_order_plan_matches_oracle_sequence(hs, cfg, order):
 
 
 def test_first_order_and_single_factor_steps_have_no_joint(hs):
-    H = config_hamiltonian(1)
+    H = workload_hamiltonian("tfim_chain_n8")
     f = hs.plan(H.strings, H.coeffs, H.n, 1.0, 10, 8)
     assert f.describe()["joint"] == -1
     f.close()

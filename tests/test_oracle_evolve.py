@@ -13,7 +13,7 @@ import scipy.linalg as sl
 
 import oracle.evolve as oev
 from oracle import factors, metrics, pauli
-from workloads import config_hamiltonian, hamiltonians as wh, states as ws
+from workloads import workload_hamiltonian, hamiltonians as wh, states as ws
 
 
 def _setup(H, budget, dt):
@@ -53,10 +53,10 @@ def test_c_oracle_matches_numpy_twin(oracle_lib):
     assert np.abs(a - b).max() < 1e-14
 
 
-@pytest.mark.parametrize("which", ["cfg1", "heis", "random"])
+@pytest.mark.parametrize("which", ["tfim8", "heis", "random"])
 def test_trotter_product_equals_expm_product(oracle_lib, which):
-    if which == "cfg1":
-        H, budget, dt, r = config_hamiltonian(1), 8, 0.1, 10
+    if which == "tfim8":
+        H, budget, dt, r = workload_hamiltonian("tfim_chain_n8"), 8, 0.1, 10
     elif which == "heis":
         H, budget, dt, r = _heis(6), 16, 0.13, 7
     else:

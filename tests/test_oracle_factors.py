@@ -3,14 +3,14 @@
 Pins: dense matrix exponentials from SciPy (a library routine independent of
 the oracle's rotation products), brute-force diagonal counts of global
 matrices, the Heisenberg-bond closed form, and partitions worked out by hand
-from the first-fit rule for the four workload configurations.
+from the first-fit rule for the four named workloads.
 """
 import numpy as np
 import pytest
 import scipy.linalg as sl
 
 from oracle import dia, factors, pauli
-from workloads import config_hamiltonian
+from workloads import workload_hamiltonian
 from workloads import hamiltonians as wh
 
 
@@ -82,25 +82,25 @@ def test_heisenberg_bond_closed_form():
     assert np.allclose(U, ref, atol=1e-15)
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
-def test_config_partitions_by_hand(cfg):
-    H = config_hamiltonian(cfg)
-    run = wh.CONFIG_RUN[cfg]
+@pytest.mark.parametrize("cfg", list(wh.WORKLOADS))
+def test_workload_partitions_by_hand(cfg):
+    H = workload_hamiltonian(cfg)
+    run = wh.WORKLOAD_RUN[cfg]
     terms = _terms(H.strings, H.coeffs, H.n)
     part = factors.first_fit(terms, run["budget"], run["t"] / run["steps"])
     kinds = [pauli.Term(s, 1).is_diagonal for s in H.strings]
     assert part.diag == [i for i, k in enumerate(kinds) if k]
-    if cfg == 1:
+    if cfg == "tfim_chain_n8":
         # ZZ bonds 0..6 then X_0..X_7 at indices 7..14; budget 8 -> pairs
         assert part.groups == [[7, 8], [9, 10], [11, 12], [13, 14]]
-    elif cfg == 2:
+    elif cfg == "heisenberg_chain_n20":
         # per bond i: XX at 3i, YY at 3i+1; bonds {0,2},{1,3},{4,6},...,{16,18},{17}
         pairs = []
         for base in range(0, 16, 4):
             pairs += [[base, base + 2], [base + 1, base + 3]]
         pairs += [[16, 18], [17]]
         assert part.groups == [[3 * b + o for b in p for o in (0, 1)] for p in pairs]
-    elif cfg == 3:
+    elif cfg == "tfim_5x5_ancilla_n26":
         # 40 ZZ bonds, then X_q at 40 + q; groups of three consecutive X
         assert part.groups == [[40 + q for q in range(s, min(s + 3, 25))] for s in range(0, 25, 3)]
     else:
@@ -108,7 +108,8 @@ def test_config_partitions_by_hand(cfg):
         assert part.groups == [[37 + q for q in range(s, s + 3)] for s in range(0, 24, 3)]
     fl = part.factor_list()
     counts = [len(factors.factor_offsets(terms, f, run["t"] / run["steps"])) for f in fl]
-    expect = {1: [7] * 4, 2: [9] * 9 + [3], 3: [15] * 8 + [3], 4: [15] * 8}[cfg]
+    expect = {"tfim_chain_n8": [7] * 4, "heisenberg_chain_n20": [9] * 9 + [3],
+              "tfim_5x5_ancilla_n26": [15] * 8 + [3], "maxcut_3reg_n24": [15] * 8}[cfg]
     assert counts == expect
     assert fl[0][0] is True            # the diagonal factor rides on the first group
 
@@ -133,10 +134,10 @@ def test_noncommuting_terms_never_share_a_group():
     assert allidx == list(range(len(terms)))
 
 
-@pytest.mark.parametrize("cfg", [1])
+@pytest.mark.parametrize("cfg", ["tfim_chain_n8"])
 def test_factor_dense_is_expm_of_factor_hamiltonian(cfg):
-    H = config_hamiltonian(cfg)
-    run = wh.CONFIG_RUN[cfg]
+    H = workload_hamiltonian(cfg)
+    run = wh.WORKLOAD_RUN[cfg]
     dt = run["t"] / run["steps"]
     terms = _terms(H.strings, H.coeffs, H.n)
     part = factors.first_fit(terms, run["budget"], dt)

@@ -1,7 +1,7 @@
 """Input generators: determinism, shapes and the structure each family must have."""
 import numpy as np
 
-from workloads import config_hamiltonian, hamiltonians as wh, states as ws
+from workloads import workload_hamiltonian, hamiltonians as wh, states as ws
 
 
 def test_states_are_unit_and_seeded():
@@ -23,13 +23,14 @@ def test_random_phase_chunking_is_invisible(monkeypatch):
     assert np.array_equal(c64, ref.astype(np.complex64))
 
 
-def test_config_shapes():
-    sizes = {1: (8, 15), 2: (20, 77), 3: (26, 65), 4: (24, 61)}
+def test_workload_shapes():
+    sizes = {"tfim_chain_n8": (8, 15), "heisenberg_chain_n20": (20, 77), "tfim_5x5_ancilla_n26": (26, 65),
+             "maxcut_3reg_n24": (24, 61)}
     for k, (n, nt) in sizes.items():
-        H = config_hamiltonian(k)
+        H = workload_hamiltonian(k)
         assert H.n == n and len(H.terms) == nt
         assert all(len(s) == n for s in H.strings)
-    H3 = config_hamiltonian(3)
+    H3 = workload_hamiltonian("tfim_5x5_ancilla_n26")
     assert all(s[25] == "I" for s in H3.strings)          # idle ancilla
     assert sum(1 for s in H3.strings if "X" in s) == 25
     assert all(c == -3.04 for s, c in H3.terms if "X" in s)

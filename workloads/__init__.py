@@ -21,12 +21,14 @@ from .hamiltonians import (  # noqa: F401
     maxcut,
     random_regular_graph,
     tsp_onehot,
-    config_hamiltonian,
+    WORKLOADS,
+    WORKLOAD_RUN,
+    workload_hamiltonian,
 )
 from .states import (  # noqa: F401
     zero_state,
     neel_state,
     uniform_state,
     random_phase_state,
-    config_states,
+    workload_states,
 )

@@ -194,27 +194,36 @@ def tsp_onehot(dist, penalty: float = 20.0) -> Hamiltonian:
     return H
 
 
-def config_hamiltonian(k: int) -> Hamiltonian:
-    """The Hamiltonian of workload configuration ``k`` (1..4), seed = k."""
-    if k == 1:
+# The four fixed workloads, by what they are (seeds are fixed per workload).
+WORKLOADS = ("tfim_chain_n8", "heisenberg_chain_n20", "tfim_5x5_ancilla_n26", "maxcut_3reg_n24")
+
+
+def workload_hamiltonian(name: str) -> Hamiltonian:
+    """The Hamiltonian of a named workload:
+    tfim_chain_n8          open TFIM chain, J = h = 1
+    heisenberg_chain_n20   open Heisenberg chain, J = 1, fields U[-1, 1] (seed 2)
+    tfim_5x5_ancilla_n26   5x5 open TFIM lattice, J = 1, h = 3.04, plus an idle qubit
+    maxcut_3reg_n24        weighted MaxCut on a random 3-regular graph (seed 4),
+                           weights U[1, 10], transverse mixer 0.7"""
+    if name == "tfim_chain_n8":
         return tfim_1d(8, J=1.0, h=1.0)
-    if k == 2:
+    if name == "heisenberg_chain_n20":
         rng = _rng(2)
         return heisenberg_1d(20, J=1.0, fields=rng.uniform(-1.0, 1.0, 20))
-    if k == 3:
+    if name == "tfim_5x5_ancilla_n26":
         return tfim_2d(5, 5, J=1.0, h=3.04, n_total=26)
-    if k == 4:
+    if name == "maxcut_3reg_n24":
         rng = _rng(4)
         edges = random_regular_graph(24, 3, rng)
         w = rng.uniform(1.0, 10.0, len(edges))
         return maxcut(24, edges, w, mixer=0.7)
-    raise ValueError(k)
+    raise ValueError(name)
 
 
-# (t, steps, budget, dtypes, batch) of configurations 1..4
-CONFIG_RUN = {
-    1: dict(t=1.0, steps=10, budget=8, dtypes=("c128",), batch=1),
-    2: dict(t=2.0, steps=100, budget=16, dtypes=("c128", "c64"), batch=1),
-    3: dict(t=1.0, steps=50, budget=16, dtypes=("c64",), batch=1),
-    4: dict(t=1.0, steps=200, budget=16, dtypes=("c64",), batch=8),
+# (t, steps, budget, dtypes, batch) of each named workload
+WORKLOAD_RUN = {
+    "tfim_chain_n8": dict(t=1.0, steps=10, budget=8, dtypes=("c128",), batch=1),
+    "heisenberg_chain_n20": dict(t=2.0, steps=100, budget=16, dtypes=("c128", "c64"), batch=1),
+    "tfim_5x5_ancilla_n26": dict(t=1.0, steps=50, budget=16, dtypes=("c64",), batch=1),
+    "maxcut_3reg_n24": dict(t=1.0, steps=200, budget=16, dtypes=("c64",), batch=8),
 }

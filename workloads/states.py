@@ -47,18 +47,21 @@ def random_phase_state(n: int, seed: int, dtype=np.complex128) -> np.ndarray:
     return out
 
 
-def config_states(k: int, dtype=np.complex128) -> np.ndarray:
-    """Initial states of configuration ``k`` as a [batch, N] array."""
-    if k == 1:
+def workload_states(name: str, dtype=np.complex128) -> np.ndarray:
+    """Initial states of a named workload as a [batch, N] array: |0..0> for
+    the n = 8 chain, the Neel state for the n = 20 chain, a random-phase state
+    (seed 3) at n = 26, and at n = 24 the uniform state plus seven
+    random-phase states (seeds 401..407)."""
+    if name == "tfim_chain_n8":
         return zero_state(8, dtype)[None, :]
-    if k == 2:
+    if name == "heisenberg_chain_n20":
         return neel_state(20, dtype)[None, :]
-    if k == 3:
+    if name == "tfim_5x5_ancilla_n26":
         return random_phase_state(26, 3, dtype)[None, :]
-    if k == 4:
+    if name == "maxcut_3reg_n24":
         out = np.empty((8, 1 << 24), dtype=dtype)
         out[0] = uniform_state(24, dtype)
         for b in range(1, 8):
             out[b] = random_phase_state(24, 4 * 100 + b, dtype)
         return out
-    raise ValueError(k)
+    raise ValueError(name)
