@@ -100,6 +100,8 @@ struct hs_factors_s {
     int device = 0;
     int *viol_dev = nullptr;
     double *work_dev = nullptr;      // [8][G][4] partials, then [8][4] records
+    double *norm_dev = nullptr;      // per-tile norm partials of the step's last launch, on demand
+    size_t norm_bytes = 0;
     void *scratch_dev = nullptr;     // output of open launches (HS_MAX_BATCH states), on demand
     size_t scratch_bytes = 0;
     hipStream_t alloc_stream = nullptr;   // device memory is stream-ordered on this stream
@@ -118,6 +120,7 @@ struct hs_factors_s {
             if (kv.second.dev_desc) (void)hipFreeAsync(kv.second.dev_desc, alloc_stream);
         if (viol_dev) (void)hipFreeAsync(viol_dev, alloc_stream);
         if (scratch_dev) (void)hipFreeAsync(scratch_dev, alloc_stream);
+        if (norm_dev) (void)hipFreeAsync(norm_dev, alloc_stream);
         if (work_dev) (void)hipFreeAsync(work_dev, alloc_stream);
     }
 };
@@ -223,8 +226,12 @@ hs_status make_evolve_plan(hs_factors_s *h, const PlanKey &key, EvolvePlan &ep, 
     return HS_OK;
 }
 
+// Whether the step's last launch can also produce the FP64 norm partials
+// (a closed tile launch whose LDS holds the per-wave sums).
+bool run_makes_norm(const Run &run) { return !run.elementwise && !run.open && run.geo.T >= 64; }
+
 hs_status launch_run(hs_factors_s *h, const EvolvePlan &ep, const Run &run, void *psi, int chunk,
-                     const double *nrm2_records, void *stream) {
+                     const double *nrm2_records, void *stream, double *norm_partials = nullptr) {
     const Plan &P = h->plan;
     const bool c128 = h->dtype == HS_C128;
     const size_t sc = elem_bytes(h->dtype);
@@ -253,6 +260,8 @@ hs_status launch_run(hs_factors_s *h, const EvolvePlan &ep, const Run &run, void
         a.nrm2 = nrm2_records ? nrm2_records + 4 * b0 : nullptr;
         a.viol = run.open ? nullptr : h->viol_dev;
         a.swizzle = ep.swizzle;
+        // partials of state b0 + b at [((b0 + b) * tiles + tile) * 4]
+        a.norm_out = norm_partials ? norm_partials + (size_t)b0 * (P.N / run.geo.T) * 4 : nullptr;
         const int nb = std::min(lbatch, chunk - b0);
         int e = hs::launch_tile(a, nb, c128, !run.open, stream);
         if (e) return hip_fail((hipError_t)e, "tile kernel launch");
@@ -458,17 +467,39 @@ hs_status hs_evolve(hs_factors f, void *psi, int batch, int steps, void *stream,
             HS_HIP(hipMallocAsync(&f->scratch_dev, bytes, hst), "hipMallocAsync(scratch)");
             f->scratch_bytes = bytes;
         }
+        if (renorm) {
+            // the step's last launch sums |y|^2 per tile: room for its partials
+            size_t need = 0;
+            for (int q = 0; q < kParts; ++q)
+                if (!ep.runs[q].empty() && run_makes_norm(ep.runs[q].back()))
+                    need = std::max(need, (size_t)chunk * (P.N / ep.runs[q].back().geo.T) * 4 * sizeof(double));
+            if (need > f->norm_bytes) {
+                hipStream_t hst = reinterpret_cast<hipStream_t>(stream);
+                if (f->norm_dev) HS_HIP(hipFreeAsync(f->norm_dev, hst), "hipFreeAsync(norm partials)");
+                f->norm_dev = nullptr;
+                f->norm_bytes = 0;
+                HS_HIP(hipMallocAsync(reinterpret_cast<void **>(&f->norm_dev), need, hst),
+                       "hipMallocAsync(norm partials)");
+                f->norm_bytes = need;
+            }
+        }
         void *p = static_cast<char *>(psi) + (size_t)c0 * P.N * sc;
         const double *rec = f->records() + 2;    // squared norm of state b at rec[4 b]
         for (int s = 0; s < steps; ++s) {
             const int part = steps == 1 ? kPartLone
                              : s == 0 ? kPartFirst : s == steps - 1 ? kPartLast : kPartMiddle;
             const std::vector<Run> &runs = ep.runs[part];
+            const bool fused_norm = renorm && run_makes_norm(runs.back());
             for (size_t ri = 0; ri < runs.size(); ++ri) {
                 const double *nrm = (renorm && s > 0 && ri == 0) ? rec : nullptr;
-                if (hs_status st = launch_run(f, ep, runs[ri], p, chunk, nrm, stream)) return st;
+                double *np = (fused_norm && ri + 1 == runs.size()) ? f->norm_dev : nullptr;
+                if (hs_status st = launch_run(f, ep, runs[ri], p, chunk, nrm, stream, np)) return st;
             }
-            if (renorm) {
+            if (fused_norm) {
+                const int tiles = (int)(P.N / runs.back().geo.T);
+                int e = hs::launch_reduce_partials(f->norm_dev, tiles, chunk, f->records(), stream);
+                if (e) return hip_fail((hipError_t)e, "norm reduction");
+            } else if (renorm) {
                 int e = hs::launch_reduce(p, f->dtype, p, f->dtype, chunk, P.N, f->partials(),
                                           hs::kReduceBlocks, f->records(), false, stream);
                 if (e) return hip_fail((hipError_t)e, "norm reduction");
@@ -631,6 +662,8 @@ hs_status hs_footprint(hs_factors f, int batch, size_t *bytes) {
         if (F.xmask_union &&
             !geometry(F.xlb, F.xhb, f->plan.n, tile_rows_max(f->dtype, 1, f->plan.N)).ok) open = true;
     if (open) total += (size_t)std::min(batch, HS_MAX_BATCH) * f->plan.N * sc;   // its scratch state
+    // per-tile norm partials when renormalising (tiles of at least 64 rows)
+    total += (size_t)std::min(batch, HS_MAX_BATCH) * (size_t)(f->plan.N / 64 + 1) * 4 * sizeof(double);
     total += sizeof(double) * ((size_t)HS_MAX_BATCH * hs::kReduceBlocks * 4 + HS_MAX_BATCH * 4);
     total += 64 * 1024;                                               // descriptors, flag
     *bytes = total;

@@ -83,6 +83,8 @@ struct TileArgs {
     const void *x0;          // Horner launches: y = x0 + alpha (A x), x0 read at the row only
     double alpha_re, alpha_im;
     int32_t ragged;          // open contiguous launch whose last tile passes row N (any N)
+    double *norm_out;        // or null: per tile and state, the FP64 sum of |y|^2 over the
+                             // tile's rows at [(b * gridDim.x + tile) * 4 + 2] (others 0)
 };
 
 struct ConstructArgs {
@@ -112,6 +114,8 @@ int launch_diag_elementwise(void *y, const void *x, const void *diag, int64_t N,
 int launch_reduce(const void *A, int ta, const void *B, int tb, int batch, int64_t N,
                   double *partial, int G, double *out, bool dot, void *stream);
 int launch_scale(void *psi, int64_t N, int batch, const double *nrm2, bool c128, void *stream);
+// records [batch][4] from per-block partials [batch][G][4], in a fixed order
+int launch_reduce_partials(const double *partial, int G, int batch, double *out, void *stream);
 
 // general operators in the diagonal layout (dia_ops.hip)
 struct PauliDiaArgs {

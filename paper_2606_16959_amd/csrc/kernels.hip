@@ -184,6 +184,13 @@ __device__ __forceinline__ void ld2_cached(const C2<double> *p, int i, C2<double
     b = C2<double>{v.x, v.y};
 }
 
+// wave64 butterfly sum (fixed order)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 template <typename R>
 __device__ __forceinline__ C2<R> cmask(C2<R> c, bool keep) {
     return keep ? c : C2<R>{(R)0, (R)0};
@@ -377,6 +384,47 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
         }
     }
 
+    if (a.norm_out) {
+        // FP64 sum of |y|^2 over the tile's rows, per state: rows in a fixed
+        // order per thread, a wave butterfly, then the waves in order.  The
+        // state tile in LDS is no longer needed once every thread is here.
+        double ss[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) ss[b] = 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+            if (i0 < T) {
+                const int r0 = row_of(i0);
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+                    if (!RAG || r0 + k < a.N)
+#pragma unroll
+                        for (int b = 0; b < B; ++b) {
+                            const double re = (double)acc[p][k][b].re, im = (double)acc[p][k][b].im;
+                            ss[b] += re * re + im * im;
+                        }
+            }
+        }
+        __syncthreads();
+        double *red = reinterpret_cast<double *>(smem_raw);
+        const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const double v = wave_sum(ss[b]);
+            if (lane == 0) red[wave * B + b] = v;
+        }
+        __syncthreads();
+        if (tid < B) {
+            double tsum = 0.0;
+            for (int w = 0; w < NT / 64; ++w) tsum += red[w * B + tid];
+            double *o = a.norm_out + ((size_t)tid * gridDim.x + blockIdx.x) * 4;
+            o[0] = 0.0;
+            o[1] = 0.0;
+            o[2] = tsum;
+            o[3] = 0.0;
+        }
+    }
     if (HORNER) {
         const C2<R> *x0 = reinterpret_cast<const C2<R> *>(a.x0);
         const C2<R> al{(R)a.alpha_re, (R)a.alpha_im};
@@ -450,11 +498,6 @@ __global__ void scale_kernel(C2<R> *psi, int64_t N, const double *nrm2) {
 // FP64; wave64 butterfly, then the four waves in fixed order.  Pass 2: one
 // block per state sums the G partials in a fixed tree.  No atomics, so the
 // result is bit-reproducible.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 template <typename TA, typename TB, bool DOT>
 __global__ __launch_bounds__(256) void reduce_partial_kernel(const void *A, const void *Bv, int64_t N,
@@ -682,6 +725,11 @@ int launch_reduce(const void *A, int ta, const void *Bv, int tb, int batch, int6
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
     hipLaunchKernelGGL(reduce_final_kernel, dim3(batch), blk, 0, S(stream), partial, G, out);
+    return (int)hipGetLastError();
+}
+
+int launch_reduce_partials(const double *partial, int G, int batch, double *out, void *stream) {
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(batch), dim3(256), 0, S(stream), partial, G, out);
     return (int)hipGetLastError();
 }
 
