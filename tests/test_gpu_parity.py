@@ -503,3 +503,28 @@ def test_maximum_size_n30_sampled_rows():
         vals = ofac.factor_entries(terms, part, fac, n, 0.3, rows[ok], d)
         ref[ok] += vals * np.array([x_at[int(c)] for c in rows[ok] + d])
     assert np.abs(got - ref).max() <= 2.0 ** -20 * amp * 4
+
+
+@pytest.mark.parametrize("order,ratio,rs", [(1, 2.0, (16, 32, 64)), (2, 4.0, (8, 16, 32)), (4, 16.0, (4, 8, 16))])
+def test_error_scaling_on_the_gpu(order, ratio, rs):
+    """complex128 GPU evolutions against exp(-iHt) (dense eigendecomposition,
+    n = 7): the global error falls by 2^order per doubling of r."""
+    hs, torch = hs_gpu()
+    import scipy.linalg as sl
+    n, t = 7, 1.0
+    H = wh.tfim_1d(n, 1.0, 1.0)
+    Hd = opauli.dense_hamiltonian(opauli.parse_terms(H.strings, H.coeffs, n), n)
+    rng = np.random.default_rng(order)
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    exact = sl.expm(-1j * t * Hd) @ psi0
+    note(f"error scaling order {order} r={rs}")
+    errs = []
+    for r in rs:
+        f = hs.build_factors(H.strings, H.coeffs, n, t, r, 8, dtype="c128", order=order)
+        p = _to_dev(torch, psi0[None], np.complex128)
+        hs.evolve(f, p, r)
+        errs.append(np.linalg.norm(p.cpu().numpy()[0] - exact))
+        f.close()
+    q = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    assert abs(q[-1] - ratio) < 0.15 * ratio, (errs, q)
