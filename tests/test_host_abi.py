@@ -191,3 +191,24 @@ def test_first_order_and_single_factor_steps_have_no_joint(hs):
         assert d["joint"] == -1 and len(d["sequence"]) == 1
         assert abs(d["factors"][0]["dt"] - 0.1) < 1e-15
         f.close()
+
+
+def test_plain_c_caller(hs, tmp_path):
+    """include/hamsim.h compiles as C99 and a C program linked against the
+    library plans a TFIM chain: four factors {X_2k, X_2k+1} with D on the
+    first, offsets {0, +-2^a, +-2^b, +-(2^b - 2^a), +-(2^a + 2^b)} = 7 each,
+    and an over-budget single term returns HS_EBUDGET with no handle."""
+    import subprocess
+    from paper_2606_16959_amd import _lib
+    exe = str(tmp_path / "abi_plan")
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                           os.path.join(ROOT, "tests", "c", "abi_plan.c"), "-o", exe,
+                           "-L", libdir, "-lhamsim", f"-Wl,-rpath,{libdir}"])
+    out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.splitlines()
+    assert out[0] == "qubits 8 factors 4 terms 15 diag_terms 7 steps 10"
+    for j in range(4):
+        a, b = 1 << (2 * j), 1 << (2 * j + 1)
+        offs = sorted({0, a, -a, b, -b, b - a, a - b, a + b, -a - b})
+        assert out[1 + j] == f"factor {j} diag {1 if j == 0 else 0} terms 2 offsets " + " ".join(map(str, offs))
+    assert out[5] == "over budget status 3 handle null"
