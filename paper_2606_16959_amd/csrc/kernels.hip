@@ -120,7 +120,8 @@ __global__ void construct_kernel(ConstructArgs a) {
 // consecutive addresses.
 //
 // A thread owns pairs of adjacent rows (local indices i, i+1 with i even;
-// W is 1 or even, so the two rows are adjacent in the state too).  For an
+// a strided tile has an even W and a contiguous one W = 1 with qb = 0, so
+// the two rows are adjacent in the state too).  For an
 // even offset the two coefficients are adjacent and 16-byte aligned
 // (diagonals start on 256-byte boundaries), so complex64 pairs are fetched
 // with one 16-byte load; odd offsets use two 8-byte loads.  Loads are issued
@@ -629,6 +630,8 @@ static int tile_dispatch_b(const TileArgs &a, int mode, void *stream) {
     const int nt = mode == kClosed ? NTC : NTO;
     const int rpt = mode == kClosed ? RPT : RPT_OPEN;
     if (a.T < 2 || a.T > nt * rpt || lds > (size_t)HS_TILE_LDS_BYTES) return (int)hipErrorInvalidValue;
+    // a thread's row pair must be adjacent state rows: strided tiles need W >= 2
+    if (a.qb != 0 && a.logW < 1) return (int)hipErrorInvalidValue;
     const bool rag = a.ragged != 0;
     if ((a.N % a.T != 0) != rag) return (int)hipErrorInvalidValue;
     if (rag && (mode == kClosed || a.qb != 0 || a.logW != 0 || a.nlw_log != 0 || a.swizzle))

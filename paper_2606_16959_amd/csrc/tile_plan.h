@@ -86,8 +86,10 @@ inline Geo geometry(int lb, int hb, int n, int Tmax) {
         g.qb = 0; g.kb = logT; g.logW = 0; g.nlw_log = 0; g.T = 1 << logT; g.ok = true;
         return g;
     }
+    // here lb >= 1, so logW = min(logT - kb, lb) is 0 only when kb == logT;
+    // a thread owns two adjacent rows, so a strided tile needs W >= 2
     const int kb = hb - lb;
-    if (kb > logT) return g;
+    if (kb >= logT) return g;
     g.qb = lb;
     g.kb = kb;
     g.logW = std::min(logT - kb, lb);

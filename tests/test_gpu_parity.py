@@ -412,6 +412,39 @@ def test_long_range_factor_takes_an_open_launch(n, dtype):
     f.close()
 
 
+@pytest.mark.parametrize("n,hi,batch,dtype", [(11, 10, 1, "c64"), (11, 10, 6, "c128"), (20, 11, 8, "c64")])
+def test_hull_filling_the_tile_levels(n, hi, batch, dtype):
+    """A factor coupling bits 1 and `hi` whose hull [1, hi+1) has exactly as
+    many levels as the tile has rows would leave one row per level (W = 1),
+    and a thread's row pair would not be adjacent: such a factor takes a
+    bigger tile for one state at a time or an open launch.  n = 11 (1024-row
+    tiles): open launch; n = 20 with 8 complex64 states (2048-row tiles): one
+    state per launch on 4096 rows.  Oracle bar, closure flag clear."""
+    hs, torch = hs_gpu()
+    s = ["I"] * n
+    s[1], s[hi] = "X", "Y"
+    H = wh.Hamiltonian(n, [("".join(s), 0.8)] + [(("I" * q) + "Z" + "I" * (n - q - 1), 0.3 + 0.1 * q)
+                                                 for q in range(n)] + [("X" + "I" * (n - 1), -0.6)])
+    npd = np.complex128 if dtype == "c128" else np.complex64
+    note(f"hull filling the tile n={n} bits 1..{hi} batch={batch} {dtype}")
+    f = hs.build_factors(H.strings, H.coeffs, n, 0.6, 4, 8, dtype=dtype, merge_diag=False)
+    rng = np.random.default_rng(n + batch)
+    psi0 = rng.normal(size=(batch, 1 << n)) + 1j * rng.normal(size=(batch, 1 << n))
+    psi0 /= np.linalg.norm(psi0, axis=1, keepdims=True)
+    p = _to_dev(torch, psi0, npd)
+    hs.evolve(f, p, 4)
+    assert f.check_closure()
+    terms = opauli.parse_terms(H.strings, H.coeffs, n)
+    part = ofac.first_fit(terms, 8, 0.15)
+    from oracle import evolve as oev
+    ref = oev.evolve(terms, part, psi0.astype(np.complex128), n, 0.15, 4, threads=oracle_threads())
+    got = p.cpu().numpy().astype(np.complex128)
+    if dtype == "c128":
+        assert np.abs(got - ref).max() <= 1e-12
+    assert np.all(fid(got, ref) >= (1 - 1e-12 if dtype == "c128" else 1 - 1e-6))
+    f.close()
+
+
 @pytest.mark.parametrize("order", [2, 4])
 def test_higher_order_full_size_tfim_5x5_n26(order):
     """The n = 26 workload with the bench's launch plan, 3 steps (first,
