@@ -1,13 +1,21 @@
-"""Seeded random Pauli Hamiltonians through the whole Trotter path against
-the oracle: random sizes (n = 4..16, so tiles are contiguous, strided or open
-for long-range couplings), supports of up to four qubits anywhere, budgets,
-product orders, merging, batches (across the 8-state chunking) and both
-dtypes."""
+"""Seeded random cases against the oracle.
+
+Trotter path: random Pauli Hamiltonians with random sizes (n = 4..16, so
+tiles are contiguous, strided or open for long-range couplings), supports of
+up to four qubits anywhere, budgets, product orders, merging, batches (across
+the 8-state chunking) and both dtypes.
+
+Operator path: random DIA operators of random size (powers of two and ragged
+N), offset structure (anywhere, multiples of 2^q reaching far, near the main
+diagonal) and zero patterns, through SpMV, SpGEMM, SpME and the fused Taylor
+update.
+"""
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
-from gpu_common import fid, hs_gpu, note, oracle_threads
-from oracle import evolve as oev, factors as ofac, pauli as opauli
+from gpu_common import fid, hs_gpu, note, oracle_threads, tol_c64
+from oracle import dia as odia, evolve as oev, factors as ofac, pauli as opauli, spme as ospme, taylor as otay
 from workloads import hamiltonians as wh
 
 pytestmark = pytest.mark.gpu
@@ -32,7 +40,7 @@ def _case(seed):
                 t=float(rng.uniform(0.1, 1.5)), dtype=str(rng.choice(["c128", "c64"])))
 
 
-@pytest.mark.parametrize("seed", range(24))
+@pytest.mark.parametrize("seed", range(32))
 def test_random_hamiltonian_matches_oracle(seed):
     hs, torch = hs_gpu()
     c = _case(seed)
@@ -66,3 +74,188 @@ def test_random_hamiltonian_matches_oracle(seed):
         assert np.abs(got - ref).max() <= 1e-11
     else:
         assert np.all(fid(got, ref) >= 1 - 1e-6)
+
+
+# ------------------------------------------------------------------ operators
+
+def _size(rng, hi):
+    if rng.integers(0, 2):
+        return 1 << int(rng.integers(1, hi.bit_length()))
+    return int(rng.integers(1, hi + 1))
+
+
+def _offsets(rng, N, kmax):
+    k = int(rng.integers(1, kmax + 1))
+    kind = int(rng.integers(0, 3))
+    if kind == 0:                                   # anywhere
+        o = rng.integers(-N + 1, N, k)
+    elif kind == 1:                                 # multiples of 2^q, reaching far
+        q = int(rng.integers(0, max(1, N.bit_length() - 1)))
+        m = max(1, (N - 1) >> q)
+        o = rng.integers(-m, m + 1, k) << q
+    else:                                           # near the main diagonal
+        o = rng.integers(-9, 10, k)
+    return sorted({int(d) for d in o if -N < d < N}) or [0]
+
+
+def _diags(rng, N, offs, npd, scale=1.0):
+    zero = float(rng.choice([0.0, 0.0, 0.5, 0.95]))
+    out = {}
+    for d in offs:
+        v = scale * (rng.normal(size=N - abs(d)) + 1j * rng.normal(size=N - abs(d)))
+        if zero:
+            v[rng.random(v.size) < zero] = 0
+        out[d] = v.astype(npd).astype(np.complex128)
+    return out
+
+
+def _hermitian(rng, N, kmax):
+    offs = [d for d in _offsets(rng, N, kmax) if d > 0]
+    D = {0: rng.normal(size=N) + 0j}
+    for d in offs:
+        v = 0.5 * (rng.normal(size=N - d) + 1j * rng.normal(size=N - d))
+        D[d], D[-d] = v, np.conj(v)
+    return D
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_spmv_matches_oracle(seed):
+    hs, torch = hs_gpu()
+    rng = np.random.default_rng(2000 + seed)
+    N = _size(rng, 1 << 17)
+    offs = _offsets(rng, N, 40)
+    B = int(rng.integers(1, 13))
+    dtype = str(rng.choice(["c128", "c64"]))
+    npd = np.complex128 if dtype == "c128" else np.complex64
+    D = _diags(rng, N, offs, npd)
+    x = (rng.normal(size=(B, N)) + 1j * rng.normal(size=(B, N))).astype(npd)
+    note(f"random spmv seed={seed} N={N} diags={len(offs)} span={offs[0]}..{offs[-1]} B={B} {dtype}")
+    dev = [torch.from_numpy(np.ascontiguousarray(D[d].astype(npd))).cuda() for d in offs]
+    y = hs.dia_spmv(offs, dev, torch.from_numpy(x).cuda())
+    got = y.cpu().numpy().astype(np.complex128)
+    ref = odia.dia_spmv(D, x.astype(np.complex128))
+    bound = odia.dia_spmv({d: np.abs(v) for d, v in D.items()}, np.abs(x.astype(np.complex128)))
+    fac = 1e-14 if dtype == "c128" else tol_c64()
+    assert np.all(np.abs(got - ref) <= fac * bound + 1e-300)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_spgemm_matches_dense_product(seed):
+    hs, torch = hs_gpu()
+    import paper_2606_16959_amd.dia as hd
+    rng = np.random.default_rng(3000 + seed)
+    N = _size(rng, 1024)
+    Da = _diags(rng, N, _offsets(rng, N, 12), np.complex128)
+    Db = _diags(rng, N, _offsets(rng, N, 12), np.complex128)
+    note(f"random spgemm seed={seed} N={N} A={len(Da)} B={len(Db)} diagonals")
+    A, B = hd.from_dict(Da, N), hd.from_dict(Db, N)
+    C = hd.spgemm(A, B)
+    ref = odia.dia_to_dense(Da, N) @ odia.dia_to_dense(Db, N)
+    got = odia.dia_to_dense(C.to_dict(), N)
+    assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    assert C.offsets == sorted({a + b for a in Da for b in Db if -N < a + b < N})
+    for X in (A, B, C):
+        X.close()
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_spme_matches_oracle(seed):
+    hs, torch = hs_gpu()
+    import paper_2606_16959_amd.dia as hd
+    rng = np.random.default_rng(4000 + seed)
+    N = _size(rng, 512)
+    D = _hermitian(rng, N, 6)
+    Href = sp.csr_matrix(odia.dia_to_dense(D, N))
+    dt = float(rng.uniform(0.02, 1.5)) / max(1.0, ospme.norm_bound(Href))
+    squarings = int(rng.choice([-1, 0, 1, 3]))
+    note(f"random spme seed={seed} N={N} diags={len(D)} dt={dt:.4g} squarings={squarings}")
+    H = hd.from_dict(D, N)
+    U, K = hd.spme(H, dt, squarings=squarings)
+    Uref, Kref, offs = ospme.spme(Href, dt, n_squarings=None if squarings < 0 else squarings)
+    assert K == Kref and U.offsets == offs
+    assert np.abs(odia.dia_to_dense(U.to_dict(), N) - Uref.toarray()).max() <= 1e-12
+    U.close()
+    H.close()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_taylor_evolve_matches_oracle(seed):
+    hs, torch = hs_gpu()
+    import paper_2606_16959_amd.dia as hd
+    rng = np.random.default_rng(5000 + seed)
+    N = _size(rng, 1 << 14)
+    D = _hermitian(rng, N, 8)
+    Href = sp.csr_matrix(odia.dia_to_dense(D, N)) if N <= 2048 else sp.dia_matrix(
+        (np.array([np.pad(D[d], (max(0, d), max(0, -d))) for d in sorted(D)]), sorted(D)), shape=(N, N)).tocsr()
+    K = int(rng.integers(1, 13))
+    steps = int(rng.integers(1, 5))
+    batch = int(rng.integers(1, 11))
+    dtype = str(rng.choice(["c128", "c64"]))
+    dt = float(rng.uniform(0.05, 0.8)) / max(1.0, ospme.norm_bound(Href))
+    npd = np.complex128 if dtype == "c128" else np.complex64
+    psi0 = rng.normal(size=(batch, N)) + 1j * rng.normal(size=(batch, N))
+    psi0 = (psi0 / np.linalg.norm(psi0, axis=1, keepdims=True)).astype(npd)
+    note(f"random taylor seed={seed} N={N} diags={len(D)} K={K} steps={steps} batch={batch} {dtype}")
+    H = hd.from_dict(D, N)
+    Hd = H if dtype == "c128" else H.to_c64()
+    psi = torch.from_numpy(psi0.copy()).cuda()
+    hd.taylor_evolve(Hd, psi, dt, K, steps)
+    ref = otay.taylor_evolve(Href, psi0.astype(np.complex128), dt, K, steps)
+    got = psi.cpu().numpy().astype(np.complex128)
+    if dtype == "c128":
+        assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    else:
+        # complex64: H rounded to FP32 and FP32 accumulation; |dt| nu <= 0.8
+        assert np.abs(got - ref).max() <= 2.0 ** -16 * np.abs(psi0).max() * 1.8 ** K * steps
+    if Hd is not H:
+        Hd.close()
+    H.close()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_operator_power_matches_oracle(seed):
+    """The Alg. 3 loop psi <- U^steps psi for a random DIA operator."""
+    hs, torch = hs_gpu()
+    import paper_2606_16959_amd.dia as hd
+    rng = np.random.default_rng(6000 + seed)
+    N = _size(rng, 1 << 15)
+    dtype = str(rng.choice(["c128", "c64"]))
+    npd = np.complex128 if dtype == "c128" else np.complex64
+    offs = _offsets(rng, N, 16)
+    D = _diags(rng, N, offs, npd, scale=1.0 / np.sqrt(len(offs)))
+    steps = int(rng.integers(1, 6))
+    batch = int(rng.integers(1, 11))
+    psi0 = (rng.normal(size=(batch, N)) + 1j * rng.normal(size=(batch, N))).astype(npd)
+    note(f"random operator power seed={seed} N={N} diags={len(offs)} steps={steps} batch={batch} {dtype}")
+    U = hd.from_dict(D, N)
+    Ud = U if dtype == "c128" else U.to_c64()
+    psi = torch.from_numpy(psi0.copy()).cuda()
+    hd.evolve(Ud, psi, steps)
+    got = psi.cpu().numpy().astype(np.complex128)
+    ref, bound = psi0.astype(np.complex128), np.abs(psi0.astype(np.complex128))
+    absD = {d: np.abs(v) for d, v in D.items()}
+    for _ in range(steps):
+        ref, bound = odia.dia_spmv(D, ref), odia.dia_spmv(absD, bound)
+    fac = 1e-14 if dtype == "c128" else tol_c64()
+    assert np.all(np.abs(got - ref) <= steps * fac * bound + 1e-300)
+    if Ud is not U:
+        Ud.close()
+    U.close()
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_step_search_matches_oracle(seed):
+    hs, torch = hs_gpu()
+    import paper_2606_16959_amd.dia as hd
+    rng = np.random.default_rng(7000 + seed)
+    n = int(rng.integers(3, 8))
+    nt = int(rng.integers(1, 7))
+    strings = ["".join(rng.choice(list("IXYZ"), size=n)) for _ in range(nt)]
+    coeffs = np.round(rng.normal(size=nt), 3)
+    Href = ospme.hamiltonian_from_strings(strings, coeffs, n)
+    budget = int(rng.integers(1, 3 * max(1, len(ospme.offsets_of(Href))) ** 2 + 1))
+    t = float(rng.uniform(0.1, 3.0))
+    note(f"random step search seed={seed} n={n} terms={nt} budget={budget} t={t:.3f}")
+    H = hd.from_pauli(strings, coeffs, n)
+    assert hd.estimate_timesteps(H, t, budget) == ospme.estimate_timesteps(Href, t, budget)
+    H.close()
