@@ -21,9 +21,9 @@ from workloads import hamiltonians as wh
 pytestmark = pytest.mark.gpu
 
 
-def _case(seed):
+def _case(seed, n_lo=4, n_hi=16, max_steps=8):
     rng = np.random.default_rng(1000 + seed)
-    n = int(rng.integers(4, 17))
+    n = int(rng.integers(n_lo, n_hi + 1))
     nt = int(rng.integers(2, 16))
     strings = []
     for _ in range(nt):
@@ -36,14 +36,24 @@ def _case(seed):
     coeffs = np.round(rng.normal(size=nt), 3)
     return dict(n=n, strings=strings, coeffs=coeffs,
                 budget=int(rng.choice([8, 16, 32, 81])), order=int(rng.choice([1, 1, 2, 4])),
-                merge=bool(rng.integers(0, 2)), steps=int(rng.integers(1, 9)), batch=int(rng.integers(1, 11)),
+                merge=bool(rng.integers(0, 2)), steps=int(rng.integers(1, max_steps + 1)),
+                batch=int(rng.integers(1, 11)),
                 t=float(rng.uniform(0.1, 1.5)), dtype=str(rng.choice(["c128", "c64"])))
 
 
 @pytest.mark.parametrize("seed", range(32))
 def test_random_hamiltonian_matches_oracle(seed):
+    _trotter_case(_case(seed), seed)
+
+
+@pytest.mark.parametrize("seed", range(104, 117))
+def test_random_hamiltonian_large_tiles_matches_oracle(seed):
+    """n = 17..22: tiles of 2048-8192 rows, strided over up to 2^12 levels."""
+    _trotter_case(_case(seed, 17, 22, 3), seed)
+
+
+def _trotter_case(c, seed):
     hs, torch = hs_gpu()
-    c = _case(seed)
     H = wh.Hamiltonian(c["n"], list(zip(c["strings"], c["coeffs"])))
     terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
     dt = c["t"] / c["steps"]
