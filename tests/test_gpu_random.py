@@ -38,7 +38,8 @@ def _case(seed, n_lo=4, n_hi=16, max_steps=8):
                 budget=int(rng.choice([8, 16, 32, 81])), order=int(rng.choice([1, 1, 2, 4])),
                 merge=bool(rng.integers(0, 2)), steps=int(rng.integers(1, max_steps + 1)),
                 batch=int(rng.integers(1, 11)),
-                t=float(rng.uniform(0.1, 1.5)), dtype=str(rng.choice(["c128", "c64"])))
+                t=float(rng.uniform(0.1, 1.5)), dtype=str(rng.choice(["c128", "c64"])),
+                renorm=bool(rng.integers(0, 2)))
 
 
 @pytest.mark.parametrize("seed", range(32))
@@ -64,22 +65,29 @@ def _trotter_case(c, seed):
             hs.plan(H.strings, H.coeffs, H.n, c["t"], c["steps"], c["budget"], order=c["order"])
         return
     note(f"random seed={seed} n={c['n']} terms={len(terms)} budget={c['budget']} order={c['order']} "
-         f"merge={c['merge']} steps={c['steps']} batch={c['batch']} {c['dtype']}")
+         f"merge={c['merge']} steps={c['steps']} batch={c['batch']} {c['dtype']} renorm={c['renorm']}")
     npd = np.complex128 if c["dtype"] == "c128" else np.complex64
     rng = np.random.default_rng(seed)
     psi0 = rng.normal(size=(c["batch"], 1 << c["n"])) + 1j * rng.normal(size=(c["batch"], 1 << c["n"]))
     psi0 /= np.linalg.norm(psi0, axis=1, keepdims=True)
+    if c["renorm"]:
+        # renormalised runs start from states of other norms: the result is
+        # the product applied to the normalised state
+        psi0 *= rng.uniform(0.2, 5.0, size=(c["batch"], 1))
     psi0 = psi0.astype(npd)
     merge = c["merge"] and c["order"] == 1
     f = hs.build_factors(H.strings, H.coeffs, H.n, c["t"], c["steps"], c["budget"], dtype=c["dtype"],
                          merge_diag=merge, order=c["order"])
     p = torch.from_numpy(psi0.copy()).cuda()
-    hs.evolve(f, p, c["steps"])
+    hs.evolve(f, p, c["steps"], renorm=c["renorm"])
     got = p.cpu().numpy().astype(np.complex128)
     assert f.check_closure()
     f.close()
-    ref = oev.evolve(terms, part, psi0.astype(np.complex128), H.n, dt, c["steps"], order=c["order"],
-                     threads=oracle_threads())
+    start = psi0.astype(np.complex128)
+    if c["renorm"]:
+        start /= np.linalg.norm(start, axis=1, keepdims=True)
+        assert np.all(np.abs(np.linalg.norm(got, axis=1) - 1.0) <= (1e-12 if c["dtype"] == "c128" else 1e-5))
+    ref = oev.evolve(terms, part, start, H.n, dt, c["steps"], order=c["order"], threads=oracle_threads())
     if c["dtype"] == "c128":
         assert np.abs(got - ref).max() <= 1e-11
     else:
