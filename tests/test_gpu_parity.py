@@ -494,48 +494,61 @@ def test_complex64_matches_the_complex128_path(cfg, steps):
     assert np.all(fid(out["c64"], out["c128"]) >= 1 - 1e-6)
 
 
-def test_maximum_size_n30_sampled_rows():
-    """n = 30, the largest state the library accepts (8 GiB complex64): one
-    step of H = 0.8 Z0 Z1 - 0.45 Z15 + 0.6 X29 (D merged into the X29 factor:
-    offsets 0 and +-2^29, a strided tile over bit 29), checked on sampled rows
-    against the oracle's factor entries applied to the input rows they
-    couple to."""
+@pytest.mark.parametrize("batch,renorm", [(1, False), (3, True)])
+def test_maximum_size_n30_sampled_rows(batch, renorm):
+    """n = 30, the largest state the library accepts (8 GiB complex64 per
+    state): one step of H = 0.8 Z0 Z1 - 0.45 Z15 + 0.6 X29 (D merged into the
+    X29 factor: offsets 0 and +-2^29, a strided tile over bit 29), checked on
+    sampled rows against the oracle's factor entries applied to the input
+    rows they couple to.  Three states with renormalisation also take the
+    fused per-tile norm over 2^30 rows per state."""
     hs, torch = hs_gpu()
     n, N = 30, 1 << 30
     strings = ["ZZ" + "I" * 28, "I" * 15 + "Z" + "I" * 14, "I" * 29 + "X"]
     coeffs = [0.8, -0.45, 0.6]
-    note("maximum size n=30 c64, one step (sampled rows)")
+    note(f"maximum size n=30 c64 batch={batch} renorm={renorm}, one step (sampled rows)")
     f = hs.build_factors(strings, coeffs, n, 0.3, 1, 8, dtype="c64")
     desc = f.describe()
     assert len(desc["factors"]) == 1 and desc["factors"][0]["offsets"] == [-(1 << 29), 0, 1 << 29]
-    # a structured-phase input built on the device: e^{2 pi i frac(r g)} / sqrt(N)
-    psi = torch.empty(N, dtype=torch.complex64, device="cuda")
-    g, amp, chunk = 0.6180339887498949, 1.0 / np.sqrt(N), 1 << 26
-    for lo in range(0, N, chunk):
-        r = torch.arange(lo, lo + chunk, dtype=torch.float64, device="cuda")
-        phi = 2.0 * np.pi * torch.frac(r * g)
-        psi[lo:lo + chunk] = torch.polar(torch.full_like(phi, amp), phi).to(torch.complex64)
-        del r, phi
+    # structured-phase inputs built on the device: e^{2 pi i frac(r g_b)} / sqrt(N)
+    psi = torch.empty(batch, N, dtype=torch.complex64, device="cuda")
+    amp, chunk = 1.0 / np.sqrt(N), 1 << 26
+    gs = [0.6180339887498949 * (b + 1) % 1.0 for b in range(batch)]
+    for b, g in enumerate(gs):
+        for lo in range(0, N, chunk):
+            r = torch.arange(lo, lo + chunk, dtype=torch.float64, device="cuda")
+            phi = 2.0 * np.pi * torch.frac(r * g)
+            psi[b, lo:lo + chunk] = torch.polar(torch.full_like(phi, amp), phi).to(torch.complex64)
+            del r, phi
     rng = np.random.default_rng(30)
     rows = np.unique(np.concatenate([np.arange(64), N - 1 - np.arange(64), (1 << 29) + np.arange(-64, 64),
                                      8192 * np.arange(1, 64) - 1, rng.integers(0, N, 4096)])).astype(np.int64)
     need = np.unique(np.concatenate([rows, rows - (1 << 29), rows + (1 << 29)]))
     need = need[(need >= 0) & (need < N)]
-    x_need = psi[torch.from_numpy(need).cuda()].cpu().numpy().astype(np.complex128)
-    x_at = dict(zip(need.tolist(), x_need.tolist()))
-    hs.evolve(f, psi, 1)
-    got = psi[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.complex128)
+    need_dev, rows_dev = torch.from_numpy(need).cuda(), torch.from_numpy(rows).cuda()
+    x_at = [dict(zip(need.tolist(), psi[b][need_dev].cpu().numpy().astype(np.complex128).tolist()))
+            for b in range(batch)]
+    hs.evolve(f, psi, 1, renorm=renorm)
+    got = [psi[b][rows_dev].cpu().numpy().astype(np.complex128) for b in range(batch)]
+    norms = hs.norm2(psi) if renorm else None
     f.close()
     del psi
     terms = opauli.parse_terms(strings, coeffs, n)
     part = ofac.first_fit(terms, 8, 0.3)
     fac = part.factor_list(merge_diag=True)[0]
-    ref = np.zeros(len(rows), dtype=np.complex128)
+    vals = {}
     for d in (-(1 << 29), 0, 1 << 29):
         ok = (rows + d >= 0) & (rows + d < N)
-        vals = ofac.factor_entries(terms, part, fac, n, 0.3, rows[ok], d)
-        ref[ok] += vals * np.array([x_at[int(c)] for c in rows[ok] + d])
-    assert np.abs(got - ref).max() <= 2.0 ** -20 * amp * 4
+        vals[d] = (ok, ofac.factor_entries(terms, part, fac, n, 0.3, rows[ok], d))
+    for b in range(batch):
+        ref = np.zeros(len(rows), dtype=np.complex128)
+        for d, (ok, v) in vals.items():
+            ref[ok] += v * np.array([x_at[b][int(c)] for c in rows[ok] + d])
+        # the inputs have unit norm up to complex64 rounding, so renormalising
+        # moves the result by far less than the bound
+        assert np.abs(got[b] - ref).max() <= 2.0 ** -20 * amp * 4
+    if renorm:
+        assert np.all(np.abs(np.asarray(norms) - 1.0) <= 1e-6)
 
 
 @pytest.mark.parametrize("order,ratio,rs", [(1, 2.0, (16, 32, 64)), (2, 4.0, (8, 16, 32)), (4, 16.0, (4, 8, 16))])
