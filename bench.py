@@ -239,8 +239,9 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, command):
 SWEEP = [
     ("default", {}),
     ("no_xcd_swizzle", {"HAMSIM_XCD_SWIZZLE": "0"}),
+    ("swizzle_all_launches", {"HAMSIM_XCD_SWIZZLE": "1"}),
+    ("swizzle_strided_only", {"HAMSIM_XCD_SWIZZLE": "2"}),
     ("wmin512", {"HAMSIM_WMIN_BYTES": "512"}),
-    ("wmin512_no_swizzle", {"HAMSIM_WMIN_BYTES": "512", "HAMSIM_XCD_SWIZZLE": "0"}),
     ("wmin1024", {"HAMSIM_WMIN_BYTES": "1024"}),
     ("wmin2048", {"HAMSIM_WMIN_BYTES": "2048"}),
     ("fuse1", {"HAMSIM_MAX_FUSE": "1"}),

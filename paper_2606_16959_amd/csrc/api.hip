@@ -259,7 +259,7 @@ hs_status launch_run(hs_factors_s *h, const EvolvePlan &ep, const Run &run, void
         a.T = run.geo.T;
         a.nrm2 = nrm2_records ? nrm2_records + 4 * b0 : nullptr;
         a.viol = run.open ? nullptr : h->viol_dev;
-        a.swizzle = ep.swizzle;
+        a.swizzle = swizzled(ep.swizzle, run.geo) ? 1 : 0;
         // partials of state b0 + b at [((b0 + b) * tiles + tile) * 4]
         a.norm_out = norm_partials ? norm_partials + (size_t)b0 * (P.N / run.geo.T) * 4 : nullptr;
         const int nb = std::min(lbatch, chunk - b0);
