@@ -86,17 +86,17 @@ def test_spme_matches_oracle(which, dt, squarings):
         d = rng.uniform(1, 10, (3, 3))
         d = np.triu(d, 1) + np.triu(d, 1).T
         Hw = wh.tsp_onehot(d, 20.0)            # 9 qubits, diagonal
-    if which == "heis" and dt == 0.8 and squarings == 0:
-        pytest.skip("unscaled series at |dt| nu ~ 16: terms near 1e6 cancel, so an absolute bar does not apply")
     note(f"spme {which} dt={dt} squarings={squarings}")
     H = hd.from_pauli(Hw.strings, Hw.coeffs, Hw.n)
     U, K = hd.spme(H, dt, squarings=squarings)
-    Uref, Kref, offs = ospme.spme(ospme.hamiltonian_from_strings(Hw.strings, Hw.coeffs, Hw.n), dt,
-                                  n_squarings=None if squarings < 0 else squarings)
+    Href = ospme.hamiltonian_from_strings(Hw.strings, Hw.coeffs, Hw.n)
+    Uref, Kref, offs = ospme.spme(Href, dt, n_squarings=None if squarings < 0 else squarings)
     assert K == Kref
     assert U.offsets == offs
     N = 1 << Hw.n
     got = odia.dia_to_dense(U.to_dict(), N)
+    # the unscaled series at |dt| nu ~ 16 (Heisenberg, dt = 0.8, s = 0) runs
+    # to K = 30 and still agrees within the same bar (measured 2e-13)
     assert np.abs(got - Uref.toarray()).max() <= 1e-12
     U.close()
     H.close()
