@@ -13,7 +13,7 @@ where a launch's algorithmic bytes are every stored coefficient of its
 factors read once plus the state read once and written once:
     sum_{factors f} sum_{d in D_f} (N - |d|) * 8  +  2 * B * N * 8.
 
-Prints ONE JSON line.  ``--gpus N`` with N > 1 exits: this build runs on a
+Prints ONE JSON line.  ``--gpus N`` with N > 1 exits: the library runs on a
 single GPU.
 """
 from __future__ import annotations
@@ -249,9 +249,9 @@ SWEEP = [
 ]
 
 
-def sweep(torch, steps, warmup, rounds=3):
+def sweep(torch, steps, warmup, passes=3):
     """Launch-plan variants of the same workload (environment knobs of the
-    library; one handle keeps a plan per setting), timed in interleaved rounds
+    library; one handle keeps a plan per setting), timed in interleaved passes
     (median); writes a summary under profiles/."""
     import paper_2606_16959_amd as hs
     from workloads import workload_hamiltonian, states as ws
@@ -281,7 +281,7 @@ def sweep(torch, steps, warmup, rounds=3):
                          "bytes": sum(per), "ms": []})
     psi = torch.from_numpy(psi0).cuda()
     ref = None
-    for rnd in range(rounds):
+    for rnd in range(passes):
         for v in variants:
             psi.copy_(torch.from_numpy(psi0).cuda())
 
@@ -301,11 +301,11 @@ def sweep(torch, steps, warmup, rounds=3):
                 out = psi.cpu().numpy()
                 v["same"] = bool(ref is None or np.array_equal(out, ref))
                 ref = out if ref is None else ref
-        log(f"sweep round {rnd} done")
+        log(f"sweep pass {rnd} done")
     md = ["# Launch-plan sweep: dia_tile_kernel, tfim2d 5x5 + ancilla, n=26, complex64", "",
           "Command (repository root, on the MI355X): `python3 bench.py --sweep`", "",
-          f"Per variant: {warmup} warm-up + {steps} timed steps, repeated in {rounds} interleaved "
-          "rounds; median ms/step. Every variant's state after the first round is compared bit for "
+          f"Per variant: {warmup} warm-up + {steps} timed steps, repeated in {passes} interleaved "
+          "passes; median ms/step. Every variant's state after the first pass is compared bit for "
           "bit with the first variant's.", "",
           "| variant | environment | launches/step | GB/step | ms/step (median) | min..max | GB/s | % of 8 TB/s | same result |",
           "|---|---|---|---|---|---|---|---|---|"]
@@ -579,7 +579,7 @@ def main():
         summarize_profiles(*args.summarize_profiles, args.profile_command)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
