@@ -176,7 +176,7 @@ constexpr int kReduceBlocks = 1024;   // partial sums per state (fixed: determin
 #define HS_TILE_ACC_C64_OPEN 8 // the same for open launches (out-of-tile gathers want more waves)
 #endif
 #ifndef HS_TILE_ACC_C128
-#define HS_TILE_ACC_C128 4     // same for complex128
+#define HS_TILE_ACC_C128 8     // same for complex128
 #endif
 #ifndef HS_TILE_LDS_BYTES
 #define HS_TILE_LDS_BYTES 131072 // largest staged tile (all states); the planner also
