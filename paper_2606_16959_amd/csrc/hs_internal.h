@@ -192,11 +192,12 @@ constexpr int tile_rpt(bool c128, int batch, bool open = false) {
     const int acc = c128 ? HS_TILE_ACC_C128 : (open ? HS_TILE_ACC_C64_OPEN : HS_TILE_ACC_C64);
     return acc / bp >= 2 ? acc / bp : 2;
 }
-// Threads per workgroup: closed complex64 launches of 5-8 states use twice
+// Threads per workgroup: closed complex64 launches of 3-8 states use twice
 // the default, so a 2048-row tile (128 KiB of LDS, one workgroup per CU) still
-// runs 16 waves per CU with one row pair per thread.
+// runs 16 waves per CU with one row pair per thread; open launches of either
+// dtype do too (8192-row tiles for one state).
 constexpr int tile_threads(bool c128, int batch, bool open = false) {
-    return (!c128 && (open || batch > 2)) ? 2 * kTileThreads : kTileThreads;
+    return (open || (!c128 && batch > 2)) ? 2 * kTileThreads : kTileThreads;
 }
 // Rows of the largest tile: all threads' rows, capped by an LDS budget.
 constexpr int tile_rows_cap(bool c128, int batch, bool open = false, int lds_bytes = HS_TILE_LDS_BYTES) {
