@@ -197,9 +197,29 @@ __device__ __forceinline__ C2<R> cmask(C2<R> c, bool keep) {
     return keep ? c : C2<R>{(R)0, (R)0};
 }
 
-#ifndef HS_TILE_PREFETCH
-#define HS_TILE_PREFETCH 0     // 1: load the next diagonal's coefficients before using this one's
+#ifndef HS_TILE_PF_ACC
+#define HS_TILE_PF_ACC 3
 #endif
+#ifndef HS_TILE_INFLIGHT
+#define HS_TILE_INFLIGHT 8     // coefficient pair loads a thread keeps outstanding (complex64; half for complex128)
+#endif
+
+// Diagonals whose coefficients a thread keeps in flight.  A thread of one or
+// two row pairs (large batches, small tiles) would otherwise wait on a single
+// short load per diagonal; it keeps about HS_TILE_INFLIGHT pair loads
+// outstanding (half as many for complex128), cut while an estimate of the
+// kernel's registers (a fixed part, per-pair indexing, the accumulators and
+// the buffers) would pass what NT threads per workgroup leave each thread.
+// Threads with more pairs already have enough loads per diagonal.
+template <typename R>
+constexpr int tile_pf(int B, int P, int NT) {
+    const int wc = (int)sizeof(R) / 2;                  // VGPRs per complex value
+    const int budget = (NT >= 1024 ? 128 : 256) - 8;
+    const int inflight = sizeof(R) == 8 ? HS_TILE_INFLIGHT / 2 : HS_TILE_INFLIGHT;
+    int pf = P <= 2 && inflight / P > 1 ? inflight / P : 1;
+    while (pf > 1 && 40 + 14 * P + HS_TILE_PF_ACC * P * B * wc + 2 * pf * P * wc > budget) --pf;
+    return pf;
+}
 
 // Coefficients of one diagonal for every row pair a thread owns (masked
 // loads: invalid rows read entry 0 and are zeroed when consumed).
@@ -301,87 +321,174 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
         }
     }
 
+    // Coefficients of PF consecutive diagonals are in flight at once: after
+    // buffer u is consumed for diagonal j it is refilled with diagonal j + PF,
+    // across factor boundaries (coefficient loads do not depend on the tile).
+    // Threads with few row pairs (large batches) keep about HS_TILE_INFLIGHT
+    // 16-byte pair loads outstanding instead of one per diagonal.
+    constexpr int PF = CLOSED ? tile_pf<R>(B, P, NT) : 1;
     const int total = a.dstart[a.nf];
-    C2<R> c[P][2];
-    load_diag<R, P, NT, RAG>(c, a.desc[0], tid, T, base, qb, logW);
-    __syncthreads();
-
     C2<R> acc[P][2][B];
     bool viol = false;
-    int dj = 0;
-    for (int f = 0; f < a.nf; ++f) {
+    auto clear_acc = [&]() {
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
             for (int k = 0; k < 2; ++k)
 #pragma unroll
                 for (int b = 0; b < B; ++b) acc[p][k][b] = C2<R>{(R)0, (R)0};
-
-        for (; dj < a.dstart[f + 1]; ++dj) {
-            const DiagDesc dd = a.desc[dj];
-            C2<R> cn[P][2];
-            if (HS_TILE_PREFETCH && dj + 1 < total) load_diag<R, P, NT, RAG>(cn, a.desc[dj + 1], tid, T, base, qb, logW);
+    };
+    // acc += (diagonal dd) x (tile in LDS), row by row
+    auto apply = [&](const C2<R> (&cc)[P][2], const DiagDesc &dd) {
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const int i0 = 2 * tid + 2 * NT * p;
-                const int r0 = row_of(i0);
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+            const int r0 = row_of(i0);
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    const int i = i0 + k;
-                    const int r = r0 + k;
-                    const bool valid = i0 < T && r >= dd.lo && r < dd.hi;
-                    const C2<R> cv = cmask(c[p][k], valid);
-                    bool in;
-                    int loc;
-                    if (dd.regular) {
-                        const int lvl = (i >> logW) + dd.m;
-                        in = (unsigned)lvl < (unsigned)L;
-                        loc = i + dd.m * W;
+            for (int k = 0; k < 2; ++k) {
+                const int i = i0 + k;
+                const int r = r0 + k;
+                const bool valid = i0 < T && r >= dd.lo && r < dd.hi;
+                const C2<R> cv = cmask(cc[p][k], valid);
+                bool in;
+                int loc;
+                if (dd.regular) {
+                    const int lvl = (i >> logW) + dd.m;
+                    in = (unsigned)lvl < (unsigned)L;
+                    loc = i + dd.m * W;
+                } else {
+                    const int pr = r + dd.off;
+                    in = (pr >> (qb + kb)) == hi && ((pr & ((1 << qb) - 1)) >> logW) == lw;
+                    loc = (((pr >> qb) & (L - 1)) << logW) | (pr & (W - 1));
+                }
+                const bool nz = cv.re != (R)0 || cv.im != (R)0;
+                const int sl = in ? loc : (i < T ? i : 0);
+                const C2<R> ce = cmask(cv, in);
+#pragma unroll
+                for (int b = 0; b < B; ++b) cfma(acc[p][k][b], ce, lds[b * T + sl]);
+                if (!in && nz) {
+                    if (CLOSED) {
+                        viol = true;
                     } else {
                         const int pr = r + dd.off;
-                        in = (pr >> (qb + kb)) == hi && ((pr & ((1 << qb) - 1)) >> logW) == lw;
-                        loc = (((pr >> qb) & (L - 1)) << logW) | (pr & (W - 1));
+#pragma unroll
+                        for (int b = 0; b < B; ++b)
+                            cfma(acc[p][k][b], cv, cscale(x[b * a.stride + pr], scale[b]));
                     }
-                    const bool nz = cv.re != (R)0 || cv.im != (R)0;
-                    const int sl = in ? loc : (i < T ? i : 0);
-                    const C2<R> ce = cmask(cv, in);
-#pragma unroll
-                    for (int b = 0; b < B; ++b) cfma(acc[p][k][b], ce, lds[b * T + sl]);
-                    if (!in && nz) {
-                        if (CLOSED) {
-                            viol = true;
-                        } else {
-                            const int pr = r + dd.off;
-#pragma unroll
-                            for (int b = 0; b < B; ++b)
-                                cfma(acc[p][k][b], cv, cscale(x[b * a.stride + pr], scale[b]));
-                        }
-                    }
-                }
-            }
-            if (!HS_TILE_PREFETCH && dj + 1 < total) {
-                load_diag<R, P, NT, RAG>(c, a.desc[dj + 1], tid, T, base, qb, logW);
-            } else {
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    c[p][0] = cn[p][0];
-                    c[p][1] = cn[p][1];
                 }
             }
         }
-        if (f + 1 < a.nf) {
-            __syncthreads();
+    };
+    // the finished factor's output becomes the next factor's input tile
+    auto acc_to_lds = [&]() {
+        __syncthreads();
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const int i0 = 2 * tid + 2 * NT * p;
-                if (i0 < T)
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+            if (i0 < T)
 #pragma unroll
-                    for (int b = 0; b < B; ++b) {
-                        lds[b * T + i0] = acc[p][0][b];
-                        lds[b * T + i0 + 1] = acc[p][1][b];
+                for (int b = 0; b < B; ++b) {
+                    lds[b * T + i0] = acc[p][0][b];
+                    lds[b * T + i0 + 1] = acc[p][1][b];
+                }
+        }
+        __syncthreads();
+    };
+
+    if constexpr (PF == 1) {
+        // the next diagonal's coefficients are loaded once this one's are used
+        C2<R> c[P][2];
+        load_diag<R, P, NT, RAG>(c, a.desc[0], tid, T, base, qb, logW);
+        __syncthreads();
+        int dj = 0;
+        for (int f = 0; f < a.nf; ++f) {
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int b = 0; b < B; ++b) acc[p][k][b] = C2<R>{(R)0, (R)0};
+            for (; dj < a.dstart[f + 1]; ++dj) {
+                const DiagDesc dd = a.desc[dj];
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const int i0 = 2 * tid + 2 * NT * p;
+                    const int r0 = row_of(i0);
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) {
+                        const int i = i0 + k;
+                        const int r = r0 + k;
+                        const bool valid = i0 < T && r >= dd.lo && r < dd.hi;
+                        const C2<R> cv = cmask(c[p][k], valid);
+                        bool in;
+                        int loc;
+                        if (dd.regular) {
+                            const int lvl = (i >> logW) + dd.m;
+                            in = (unsigned)lvl < (unsigned)L;
+                            loc = i + dd.m * W;
+                        } else {
+                            const int pr = r + dd.off;
+                            in = (pr >> (qb + kb)) == hi && ((pr & ((1 << qb) - 1)) >> logW) == lw;
+                            loc = (((pr >> qb) & (L - 1)) << logW) | (pr & (W - 1));
+                        }
+                        const bool nz = cv.re != (R)0 || cv.im != (R)0;
+                        const int sl = in ? loc : (i < T ? i : 0);
+                        const C2<R> ce = cmask(cv, in);
+#pragma unroll
+                        for (int b = 0; b < B; ++b) cfma(acc[p][k][b], ce, lds[b * T + sl]);
+                        if (!in && nz) {
+                            if (CLOSED) {
+                                viol = true;
+                            } else {
+                                const int pr = r + dd.off;
+#pragma unroll
+                                for (int b = 0; b < B; ++b)
+                                    cfma(acc[p][k][b], cv, cscale(x[b * a.stride + pr], scale[b]));
+                            }
+                        }
                     }
+                }
+                if (dj + 1 < total) load_diag<R, P, NT, RAG>(c, a.desc[dj + 1], tid, T, base, qb, logW);
             }
-            __syncthreads();
+            if (f + 1 < a.nf) {
+                __syncthreads();
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const int i0 = 2 * tid + 2 * NT * p;
+                    if (i0 < T)
+#pragma unroll
+                        for (int b = 0; b < B; ++b) {
+                            lds[b * T + i0] = acc[p][0][b];
+                            lds[b * T + i0 + 1] = acc[p][1][b];
+                        }
+                }
+                __syncthreads();
+            }
+        }
+    } else {
+        C2<R> c[PF][P][2];
+#pragma unroll
+        for (int u = 0; u < PF; ++u)
+            if (u < total) load_diag<R, P, NT, RAG>(c[u], a.desc[u], tid, T, base, qb, logW);
+        __syncthreads();
+        clear_acc();
+        int f = 0, fend = a.dstart[1];
+        for (int d0 = 0; d0 < total; d0 += PF) {
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+                const int dj = d0 + u;
+                if (dj < total) {                 // uniform over the workgroup
+                    if (dj == fend) {             // first diagonal of the next factor
+                        acc_to_lds();
+                        clear_acc();
+                        ++f;
+                        fend = a.dstart[f + 1];
+                    }
+                    const DiagDesc dd = a.desc[dj];
+                    apply(c[u], dd);
+                    if (dj + PF < total) load_diag<R, P, NT, RAG>(c[u], a.desc[dj + PF], tid, T, base, qb, logW);
+                }
+            }
         }
     }
 
