@@ -260,6 +260,7 @@ hs_status launch_run(hs_factors_s *h, const EvolvePlan &ep, const Run &run, void
         a.nrm2 = nrm2_records ? nrm2_records + 4 * b0 : nullptr;
         a.viol = run.open ? nullptr : h->viol_dev;
         a.swizzle = swizzled(ep.swizzle, run.geo) ? 1 : 0;
+        a.stream_out = stream_out(chunk, P.N, h->dtype);
         // partials of state b0 + b at [((b0 + b) * tiles + tile) * 4]
         a.norm_out = norm_partials ? norm_partials + (size_t)b0 * (P.N / run.geo.T) * 4 : nullptr;
         const int nb = std::min(lbatch, chunk - b0);
@@ -716,7 +717,8 @@ hs_status hs_dia_spmv(int n_diags, const long long *offsets, const void *const *
         HS_HIP(hipMallocAsync(reinterpret_cast<void **>(&ddev), sizeof(DiagDesc) * n_diags, st),
                "hipMallocAsync(descriptors)");
         hipError_t e = hipMemcpyAsync(ddev, hd.data(), sizeof(DiagDesc) * n_diags, hipMemcpyHostToDevice, st);
-        const TileArgs a = open_args(geo, ddev, n_diags, xb + (size_t)c0 * N * sc, yb + (size_t)c0 * N * sc, N);
+        TileArgs a = open_args(geo, ddev, n_diags, xb + (size_t)c0 * N * sc, yb + (size_t)c0 * N * sc, N);
+        a.stream_out = stream_out(chunk, N, dtype);
         if (e == hipSuccess) e = (hipError_t)hs::launch_tile(a, chunk, dtype == HS_C128, false, stream);
         hipError_t e2 = hipStreamSynchronize(st);
         (void)hipFreeAsync(ddev, st);

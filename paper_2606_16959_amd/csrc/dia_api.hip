@@ -710,7 +710,8 @@ hs_status hs_dia_evolve(hs_dia U, void *psi, int batch, int steps, void *stream)
         char *home = cur;
         char *other = static_cast<char *>(scratch);
         for (int s = 0; s < steps; ++s) {
-            const TileArgs a = open_args(geo, dd, nd, cur, other, N);
+            TileArgs a = open_args(geo, dd, nd, cur, other, N);
+            a.stream_out = stream_out(chunk, N, U->dtype);
             int le = hs::launch_tile(a, chunk, U->dtype == HS_C128, false, st);
             if (le) return dhip((hipError_t)le, "tile kernel launch");
             std::swap(cur, other);
@@ -807,6 +808,7 @@ hs_status hs_taylor_evolve(hs_dia H, void *psi, int batch, double dt, int K, int
             for (int j = K; j >= 1; --j) {
                 void *out = (K == 1) ? other : (j == 1 ? cur : buf[(K - j) & 1]);
                 TileArgs a = open_args(geo, dd, nd, w, out, N);
+                a.stream_out = stream_out(chunk, N, H->dtype);
                 a.x0 = cur;
                 a.alpha_re = 0.0;
                 a.alpha_im = -dt / j;

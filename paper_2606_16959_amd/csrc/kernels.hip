@@ -171,6 +171,30 @@ __device__ __forceinline__ void ld2(const C2<double> *p, int i, C2<double> &a, C
     b = ld1(p, i + 1);
 }
 
+typedef __attribute__((address_space(1))) f4v g_f4w;
+typedef __attribute__((address_space(1))) d2v g_d2w;
+// rows i and i + 1 (i even) of an output state: one 16-byte store for
+// complex64, two for complex128; STREAM streams them past the caches (a
+// compile-time choice: with a run-time branch the compiler merges the two
+// stores and drops the hint)
+template <bool STREAM>
+__device__ __forceinline__ void st2(C2<float> *p, int i, C2<float> a, C2<float> b) {
+    const f4v v = {a.re, a.im, b.re, b.im};
+    if (STREAM) __builtin_nontemporal_store(v, (g_f4w *)(p) + (i >> 1));
+    else *((g_f4w *)(p) + (i >> 1)) = v;
+}
+template <bool STREAM>
+__device__ __forceinline__ void st2(C2<double> *p, int i, C2<double> a, C2<double> b) {
+    const d2v u = {a.re, a.im}, v = {b.re, b.im};
+    if (STREAM) {
+        __builtin_nontemporal_store(u, (g_d2w *)(p) + i);
+        __builtin_nontemporal_store(v, (g_d2w *)(p) + i + 1);
+    } else {
+        *((g_d2w *)(p) + i) = u;
+        *((g_d2w *)(p) + i + 1) = v;
+    }
+}
+
 // State rows staged by open launches keep the default cache policy: other
 // tiles read them again as out-of-tile partners, and those reads should hit.
 __device__ __forceinline__ void ld2_cached(const C2<float> *p, int i, C2<float> &a, C2<float> &b) {
@@ -259,7 +283,9 @@ __device__ __forceinline__ void load_diag(C2<R> (&c)[P][2], const DiagDesc &dd, 
 // one Horner stage of a polynomial in A applied to a state.
 // RAG (open contiguous launches only): N need not be a multiple of the tile;
 // rows at or past N are neither loaded nor stored.
-template <typename R, int B, int RPT, bool CLOSED, bool HORNER = false, int NT = kTileThreads, bool RAG = false>
+// STREAM (not with RAG): the output is written with non-temporal stores.
+template <typename R, int B, int RPT, bool CLOSED, bool HORNER = false, int NT = kTileThreads, bool RAG = false,
+          bool STREAM = false>
 __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
     static_assert(RPT % 2 == 0, "rows come in pairs");
     constexpr int P = RPT / 2;
@@ -564,8 +590,12 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
             const int r0 = row_of(i0);
 #pragma unroll
             for (int b = 0; b < B; ++b) {
-                if (!RAG || r0 < a.N) y[b * a.stride + r0] = acc[p][0][b];
-                if (!RAG || r0 + 1 < a.N) y[b * a.stride + r0 + 1] = acc[p][1][b];
+                if (!RAG) {
+                    st2<STREAM>(y + b * a.stride, r0, acc[p][0][b], acc[p][1][b]);
+                } else {
+                    if (!RAG || r0 < a.N) y[b * a.stride + r0] = acc[p][0][b];
+                    if (!RAG || r0 + 1 < a.N) y[b * a.stride + r0 + 1] = acc[p][1][b];
+                }
             }
         }
     }
@@ -696,13 +726,13 @@ static std::mutex &lds_attr_mutex() {
 // Launch with the smallest rows-per-thread instantiation (power of two, down
 // to one row pair) that still gives every tile row a thread: a tile smaller
 // than the kernel's capacity would otherwise issue masked loads and FMAs.
-template <typename R, int B, int RPT, bool CLOSED, bool HORNER, int NT, bool RAG = false>
+template <typename R, int B, int RPT, bool CLOSED, bool HORNER, int NT, bool RAG = false, bool STREAM = false>
 static int tile_launch(const TileArgs &a, int rows_per_thread, size_t lds, int grid, void *stream) {
     if constexpr (RPT > 2) {
         if (rows_per_thread <= RPT / 2)
-            return tile_launch<R, B, RPT / 2, CLOSED, HORNER, NT, RAG>(a, rows_per_thread, lds, grid, stream);
+            return tile_launch<R, B, RPT / 2, CLOSED, HORNER, NT, RAG, STREAM>(a, rows_per_thread, lds, grid, stream);
     }
-    auto kern = dia_tile_kernel<R, B, RPT, CLOSED, HORNER, NT, RAG>;
+    auto kern = dia_tile_kernel<R, B, RPT, CLOSED, HORNER, NT, RAG, STREAM>;
     if (lds > 65536) {
         // allow this instantiation the dynamic LDS the launch needs (raised
         // only when a larger launch arrives; the planner keeps lds within the
@@ -745,12 +775,17 @@ static int tile_dispatch_b(const TileArgs &a, int mode, void *stream) {
         return (int)hipErrorInvalidValue;
     const int grid = (int)((a.N + a.T - 1) / a.T);
     const int need = (a.T + nt - 1) / nt;
-    if (mode == kClosed) return tile_launch<R, B, RPT, true, false, NTC>(a, need, lds, grid, stream);
+    const bool st = a.stream_out != 0;         // ragged launches keep plain stores
+    if (mode == kClosed)
+        return st ? tile_launch<R, B, RPT, true, false, NTC, false, true>(a, need, lds, grid, stream)
+                  : tile_launch<R, B, RPT, true, false, NTC>(a, need, lds, grid, stream);
     if (mode == kOpen)
-        return rag ? tile_launch<R, B, RPT_OPEN, false, false, NTO, true>(a, need, lds, grid, stream)
-                   : tile_launch<R, B, RPT_OPEN, false, false, NTO>(a, need, lds, grid, stream);
-    return rag ? tile_launch<R, B, RPT_OPEN, false, true, NTO, true>(a, need, lds, grid, stream)
-               : tile_launch<R, B, RPT_OPEN, false, true, NTO>(a, need, lds, grid, stream);
+        return rag  ? tile_launch<R, B, RPT_OPEN, false, false, NTO, true>(a, need, lds, grid, stream)
+               : st ? tile_launch<R, B, RPT_OPEN, false, false, NTO, false, true>(a, need, lds, grid, stream)
+                    : tile_launch<R, B, RPT_OPEN, false, false, NTO>(a, need, lds, grid, stream);
+    return rag  ? tile_launch<R, B, RPT_OPEN, false, true, NTO, true>(a, need, lds, grid, stream)
+           : st ? tile_launch<R, B, RPT_OPEN, false, true, NTO, false, true>(a, need, lds, grid, stream)
+                : tile_launch<R, B, RPT_OPEN, false, true, NTO>(a, need, lds, grid, stream);
 }
 
 template <typename R>

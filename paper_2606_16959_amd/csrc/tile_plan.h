@@ -162,6 +162,11 @@ inline void fill_descs(const long long *offsets, const void *const *ptrs, int nd
     }
 }
 
+// Whether launches over `chunk` states of N rows write with non-temporal stores.
+inline int32_t stream_out(int chunk, long long N, int dtype) {
+    return (size_t)chunk * (size_t)N * elem_bytes(dtype) >= kStreamOutBytes ? 1 : 0;
+}
+
 inline TileArgs open_args(const Geo &geo, const DiagDesc *ddev, int nd, const void *x, void *y, long long N) {
     TileArgs a{};
     a.y = y;
@@ -177,6 +182,7 @@ inline TileArgs open_args(const Geo &geo, const DiagDesc *ddev, int nd, const vo
     a.viol = nullptr;
     a.swizzle = 0;
     a.ragged = (N % geo.T) != 0;
+    a.stream_out = 0;
     return a;
 }
 
