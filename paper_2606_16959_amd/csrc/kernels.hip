@@ -222,7 +222,7 @@ __device__ __forceinline__ C2<R> cmask(C2<R> c, bool keep) {
 }
 
 #ifndef HS_TILE_PF_ACC
-#define HS_TILE_PF_ACC 3
+#define HS_TILE_PF_ACC 3       // registers counted per accumulator register in tile_pf's estimate
 #endif
 #ifndef HS_TILE_INFLIGHT
 #define HS_TILE_INFLIGHT 8     // coefficient pair loads a thread keeps outstanding (complex64; half for complex128)
@@ -422,7 +422,10 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
     };
 
     if constexpr (PF == 1) {
-        // the next diagonal's coefficients are loaded once this one's are used
+        // The next diagonal's coefficients are loaded once this one's are
+        // used.  The body is `apply` written out: this form compiles to the
+        // code the one-state kernels were tuned and profiled with (the lambda
+        // form schedules slightly differently).
         C2<R> c[P][2];
         load_diag<R, P, NT, RAG>(c, a.desc[0], tid, T, base, qb, logW);
         __syncthreads();
