@@ -88,8 +88,9 @@ struct TileArgs {
     int32_t stream_out;      // write y with non-temporal stores (see kStreamOutBytes)
 };
 
-// States of at least this many bytes (the states one call evolves together)
-// are written with non-temporal stores: they cannot stay in the 256 MB
+// States of at least this many bytes (the chunk of up to HS_MAX_BATCH states
+// that a call takes through all its launches before the next chunk) are
+// written with non-temporal stores: they cannot stay in the 256 MB
 // last-level cache until the next launch reads them, and streaming them past
 // it measured 3-6% faster; smaller states keep the default policy so that the
 // next launch finds them cached.
