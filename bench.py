@@ -500,7 +500,8 @@ def taylor_leg(torch, cases=None, timed_steps=3):
                "ms_per_step": round(ms, 4), "ms_per_stage": round(ms / K, 4),
                "gb_per_stage": round(stage_bytes / 1e9, 3),
                "gbs": round(stage_bytes * K / ms / 1e6, 1),
-               "full_run_s_estimate": round(ms * r / 1e3, 3)}
+               "full_run_s_estimate": round(ms * r / 1e3, 3),
+               "dispatches": K * (1 + timed_steps)}
         row["frac_of_peak"] = round(row["gbs"] / HBM_PEAK_GBS, 4)
         out.append(row)
         log(f"taylor {name}: r={r} K={K} {ms:.3f} ms/step {row['gbs']} GB/s; t=1 in {row['full_run_s_estimate']} s")
@@ -508,6 +509,92 @@ def taylor_leg(torch, cases=None, timed_steps=3):
         del psi
         torch.cuda.empty_cache()
     return out
+
+
+def _template_args(kernel_name):
+    """Template arguments of a kernel name as printed by rocprofv3."""
+    inner = kernel_name[kernel_name.index("<") + 1:kernel_name.rindex(">")]
+    return [a.strip() for a in inner.split(",")]
+
+
+def summarize_taylor_profiles(trace_dir, fetch_dir, write_dir, leg_output):
+    """Per-stage time and HBM traffic of the fused Taylor update from a
+    rocprofv3 kernel trace and FETCH_SIZE / WRITE_SIZE runs of
+    `bench.py --leg taylor`, against the algorithmic bytes the leg itself
+    reports (`leg_output`: a file holding the leg's JSON line, e.g. the
+    profiled run's log).  The counters are scaled by the copy calibration
+    stored with the tile kernel's traffic summary."""
+    import csv
+    import statistics
+    rows = None
+    with open(leg_output) as fh:
+        for line in fh:
+            if line.startswith('{"leg"'):
+                rows = json.loads(line)["result"]
+                break
+    if rows is None:
+        raise SystemExit(f"no taylor leg output in {leg_output}")
+    for r in rows:                     # the leg runs 1 warm-up + 3 timed steps of K stages
+        r.setdefault("dispatches", r["taylor_terms"] * 4)
+    with open(TRAFFIC_FILE) as fh:
+        cal = json.load(fh)
+    f_scale, w_scale = cal["fetch_scale"], cal["write_scale"]
+
+    def horner(name):                  # dia_tile_kernel with HORNER = true
+        return name.startswith("void hs::dia_tile_kernel<") and _template_args(name)[4] == "true"
+
+    def counters(d, cname):
+        recs = [r for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv")))
+                if r["Counter_Name"] == cname and horner(r["Kernel_Name"])]
+        recs.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return [float(r["Counter_Value"]) for r in recs]
+    fetch, write = counters(fetch_dir, "FETCH_SIZE"), counters(write_dir, "WRITE_SIZE")
+    trace = [r for r in csv.DictReader(open(os.path.join(trace_dir, "run_kernel_trace.csv"))) if horner(r["Kernel_Name"])]
+    trace.sort(key=lambda r: int(r["Dispatch_Id"]))
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in trace]
+    need = sum(r["dispatches"] for r in rows)
+    if not (len(fetch) == len(write) == len(durs) == need):
+        raise SystemExit(f"dispatch counts differ: fetch {len(fetch)} write {len(write)} trace {len(durs)} leg {need}")
+    stats = list(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_stats.csv"))))
+    ksum = ", ".join(f"{r['workload']} (K = {r['taylor_terms']}, {r['h_diagonals']} diagonals of H, "
+                     f"{r['dispatches']} dispatches)" for r in rows)
+    leg = "python3 -u bench.py --leg taylor"
+    cmd = (f"rocprofv3 --kernel-trace --stats --output-format csv -d OUT/tay_trace -o run -- {leg} > OUT/tay_trace.log; "
+           f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/tay_fetch -o run -- {leg}; "
+           f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/tay_write -o run -- {leg}; "
+           "python3 bench.py --out-dir OUT --summarize-taylor-profiles OUT/tay_trace OUT/tay_fetch OUT/tay_write "
+           "OUT/tay_trace.log")
+    md = ["# Horner stage of the fused Taylor update (dia_tile_kernel, open tiles, Horner epilogue), complex64", "",
+          f"Workloads: {ksum}. r = smallest step count with |dt| nu(H) <= 1, K stages per step (tolerance 1e-6), "
+          "1 warm-up + 3 timed steps per workload.", "",
+          "Command (repository root, on the MI355X):", "", "```", cmd, "```", "",
+          "## rocprofv3 --kernel-trace --stats", "",
+          "| kernel | calls | avg us | min us | max us | % |", "|---|---|---|---|---|---|"]
+    for r in stats[:6]:
+        md.append(f"| {r['Name'][:95]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                  f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    md += ["", "## Per Horner stage (averages over each workload's dispatches)", "",
+           f"FETCH_SIZE is scaled by {f_scale:.4f} and WRITE_SIZE by {w_scale:.4f}, the factors a 2 GiB device copy "
+           f"gives (`{os.path.relpath(TRAFFIC_FILE, ROOT)}`). Algorithmic bytes: every stored diagonal of H once "
+           "plus three state passes (w, the step input in the epilogue, the output).", "",
+           "| workload | avg ms | FETCH KiB | WRITE KiB | scaled HBM GB | algorithmic GB | algorithmic GB/s | "
+           "HBM / algorithmic |", "|---|---|---|---|---|---|---|---|"]
+    lo = 0
+    for r in rows:
+        hi = lo + r["dispatches"]
+        fk, wk, ms = statistics.mean(fetch[lo:hi]), statistics.mean(write[lo:hi]), statistics.mean(durs[lo:hi])
+        meas = (fk * f_scale + wk * w_scale) * 1024 / 1e9
+        alg = r["gb_per_stage"]
+        md.append(f"| {r['workload']} | {ms:.3f} | {fk:.0f} | {wk:.0f} | {meas:.3f} | {alg:.3f} | "
+                  f"{alg / ms * 1e3:.0f} | {meas / alg:.3f} |")
+        lo = hi
+    md += ["", "The excess over the algorithmic bytes is re-reads of w by out-of-tile partner gathers: H flips "
+           "every qubit, a tile is closed over 13 of them, and far partners are no longer in L2 or the last-level "
+           "cache when they are gathered."]
+    path = os.path.join(OUT_DIR, "dia_tile_horner_tfim_n24_n26.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md[-6:]))
 
 
 def write_serve_summary(stats, command, fname):
@@ -594,6 +681,8 @@ def main():
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
                     help="write profiles/ summaries from rocprofv3 output directories")
     ap.add_argument("--profile-command", default="")
+    ap.add_argument("--summarize-taylor-profiles", nargs=4, metavar=("TRACE", "FETCH", "WRITE", "LEG_OUTPUT"),
+                    help="write the fused Taylor update's profile summary from rocprofv3 output directories")
     ap.add_argument("--sweep", action="store_true", help="launch-plan variants (writes profiles/)")
     ap.add_argument("--out-dir", default=None, help="directory for written summaries (default profiles/)")
     args = ap.parse_args()
@@ -603,6 +692,9 @@ def main():
         os.makedirs(OUT_DIR, exist_ok=True)
     if args.summarize_profiles:
         summarize_profiles(*args.summarize_profiles, args.profile_command)
+        return
+    if args.summarize_taylor_profiles:
+        summarize_taylor_profiles(*args.summarize_taylor_profiles)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
