@@ -421,6 +421,69 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
         __syncthreads();
     };
 
+    // Open launches: a row whose partner lies outside the tile gathers it
+    // from global memory.  For complex64 launches of one or two states the
+    // gathers of G row pairs are issued before any is used (the gathered
+    // values take 8 registers), so their latencies overlap; each row still
+    // adds its LDS term first and its gathered term second, as the
+    // one-row-at-a-time order would.  Other open launches have no registers
+    // to spare (open complex128 and larger batches run at the 128-register
+    // limit of 1024-thread workgroups) and gather row by row in the loop below.
+    constexpr int kGather = sizeof(R) == 8 ? 0 : 8 / (2 * B * 2);
+    constexpr int G = kGather >= P ? P : (kGather >= 1 ? kGather : 1);
+    auto apply_open = [&](const C2<R> (&cc)[P][2], const DiagDesc &dd) {
+#pragma unroll
+        for (int g0 = 0; g0 < P; g0 += G) {
+            C2<R> gv[G][2][B];
+            C2<R> gc[G][2];
+            bool gn[G][2];
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                const int p = g0 + q;
+                const int i0 = 2 * tid + 2 * NT * p;
+                const int r0 = row_of(i0);
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int i = i0 + k;
+                    const int r = r0 + k;
+                    const bool valid = i0 < T && r >= dd.lo && r < dd.hi;
+                    const C2<R> cv = cmask(cc[p][k], valid);
+                    bool in;
+                    int loc;
+                    if (dd.regular) {
+                        const int lvl = (i >> logW) + dd.m;
+                        in = (unsigned)lvl < (unsigned)L;
+                        loc = i + dd.m * W;
+                    } else {
+                        const int pr = r + dd.off;
+                        in = (pr >> (qb + kb)) == hi && ((pr & ((1 << qb) - 1)) >> logW) == lw;
+                        loc = (((pr >> qb) & (L - 1)) << logW) | (pr & (W - 1));
+                    }
+                    const bool nz = cv.re != (R)0 || cv.im != (R)0;
+                    const int sl = in ? loc : (i < T ? i : 0);
+                    const C2<R> ce = cmask(cv, in);
+#pragma unroll
+                    for (int b = 0; b < B; ++b) cfma(acc[p][k][b], ce, lds[b * T + sl]);
+                    gn[q][k] = !in && nz;
+                    gc[q][k] = cv;
+                    if (gn[q][k]) {
+                        const int pr = r + dd.off;
+#pragma unroll
+                        for (int b = 0; b < B; ++b) gv[q][k][b] = x[b * a.stride + pr];
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < G; ++q)
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+                    if (gn[q][k])
+#pragma unroll
+                        for (int b = 0; b < B; ++b)
+                            cfma(acc[g0 + q][k][b], gc[q][k], cscale(gv[q][k][b], scale[b]));
+        }
+    };
+
     if constexpr (PF == 1) {
         // The next diagonal's coefficients are loaded once this one's are
         // used.  The body is `apply` written out: this form compiles to the
@@ -439,40 +502,44 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
                     for (int b = 0; b < B; ++b) acc[p][k][b] = C2<R>{(R)0, (R)0};
             for (; dj < a.dstart[f + 1]; ++dj) {
                 const DiagDesc dd = a.desc[dj];
+                if constexpr (!CLOSED && kGather > 0) {
+                    apply_open(c, dd);
+                } else {
 #pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const int i0 = 2 * tid + 2 * NT * p;
-                    const int r0 = row_of(i0);
+                    for (int p = 0; p < P; ++p) {
+                        const int i0 = 2 * tid + 2 * NT * p;
+                        const int r0 = row_of(i0);
 #pragma unroll
-                    for (int k = 0; k < 2; ++k) {
-                        const int i = i0 + k;
-                        const int r = r0 + k;
-                        const bool valid = i0 < T && r >= dd.lo && r < dd.hi;
-                        const C2<R> cv = cmask(c[p][k], valid);
-                        bool in;
-                        int loc;
-                        if (dd.regular) {
-                            const int lvl = (i >> logW) + dd.m;
-                            in = (unsigned)lvl < (unsigned)L;
-                            loc = i + dd.m * W;
-                        } else {
-                            const int pr = r + dd.off;
-                            in = (pr >> (qb + kb)) == hi && ((pr & ((1 << qb) - 1)) >> logW) == lw;
-                            loc = (((pr >> qb) & (L - 1)) << logW) | (pr & (W - 1));
-                        }
-                        const bool nz = cv.re != (R)0 || cv.im != (R)0;
-                        const int sl = in ? loc : (i < T ? i : 0);
-                        const C2<R> ce = cmask(cv, in);
-#pragma unroll
-                        for (int b = 0; b < B; ++b) cfma(acc[p][k][b], ce, lds[b * T + sl]);
-                        if (!in && nz) {
-                            if (CLOSED) {
-                                viol = true;
+                        for (int k = 0; k < 2; ++k) {
+                            const int i = i0 + k;
+                            const int r = r0 + k;
+                            const bool valid = i0 < T && r >= dd.lo && r < dd.hi;
+                            const C2<R> cv = cmask(c[p][k], valid);
+                            bool in;
+                            int loc;
+                            if (dd.regular) {
+                                const int lvl = (i >> logW) + dd.m;
+                                in = (unsigned)lvl < (unsigned)L;
+                                loc = i + dd.m * W;
                             } else {
                                 const int pr = r + dd.off;
+                                in = (pr >> (qb + kb)) == hi && ((pr & ((1 << qb) - 1)) >> logW) == lw;
+                                loc = (((pr >> qb) & (L - 1)) << logW) | (pr & (W - 1));
+                            }
+                            const bool nz = cv.re != (R)0 || cv.im != (R)0;
+                            const int sl = in ? loc : (i < T ? i : 0);
+                            const C2<R> ce = cmask(cv, in);
 #pragma unroll
-                                for (int b = 0; b < B; ++b)
-                                    cfma(acc[p][k][b], cv, cscale(x[b * a.stride + pr], scale[b]));
+                            for (int b = 0; b < B; ++b) cfma(acc[p][k][b], ce, lds[b * T + sl]);
+                            if (!in && nz) {
+                                if (CLOSED) {
+                                    viol = true;
+                                } else {
+                                    const int pr = r + dd.off;
+#pragma unroll
+                                    for (int b = 0; b < B; ++b)
+                                        cfma(acc[p][k][b], cv, cscale(x[b * a.stride + pr], scale[b]));
+                                }
                             }
                         }
                     }
