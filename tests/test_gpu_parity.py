@@ -494,6 +494,33 @@ def test_complex64_matches_the_complex128_path(cfg, steps):
     assert np.all(fid(out["c64"], out["c128"]) >= 1 - 1e-6)
 
 
+def test_streamed_and_cached_stores_give_the_same_bits():
+    """Launches whose states reach 128 MiB write them with non-temporal
+    stores (a kernel instantiation of its own); smaller ones keep plain
+    stores.  At n = 23 (complex64) one state is 64 MiB and two are 128 MiB:
+    the pair evolved together must equal each state evolved alone, bit for
+    bit, and match the oracle."""
+    hs, torch = hs_gpu()
+    n = 23
+    H = wh.tfim_1d(n, 1.0, 0.8)
+    note("n=23 complex64: 2 states (streamed stores) vs 1 state (plain stores)")
+    f = hs.build_factors(H.strings, H.coeffs, n, 0.3, 3, 8, dtype="c64")
+    psi0 = np.stack([ws.random_phase_state(n, 41, np.complex64), ws.random_phase_state(n, 42, np.complex64)])
+    pair = _to_dev(torch, psi0, np.complex64)
+    hs.evolve(f, pair, 3)
+    for b in range(2):
+        one = _to_dev(torch, psi0[b:b + 1], np.complex64)
+        hs.evolve(f, one, 3)
+        assert np.array_equal(one.cpu().numpy()[0], pair.cpu().numpy()[b])
+    assert f.check_closure()
+    f.close()
+    terms = opauli.parse_terms(H.strings, H.coeffs, n)
+    part = ofac.first_fit(terms, 8, 0.1)
+    from oracle import evolve as oev
+    ref = oev.evolve(terms, part, psi0.astype(np.complex128), n, 0.1, 3, threads=oracle_threads())
+    assert np.all(fid(pair.cpu().numpy().astype(np.complex128), ref) >= 1 - 1e-6)
+
+
 @pytest.mark.parametrize("batch,renorm", [(1, False), (3, True)])
 def test_maximum_size_n30_sampled_rows(batch, renorm):
     """n = 30, the largest state the library accepts (8 GiB complex64 per
