@@ -110,6 +110,15 @@ def dense_hamiltonian(terms, n: int) -> np.ndarray:
     return H
 
 
+def dense_propagator(Hd: np.ndarray, t: float) -> np.ndarray:
+    """exp(-i H t) of a dense Hermitian matrix by its eigendecomposition
+    H = V diag(w) V^dagger (numpy.linalg.eigh): V diag(exp(-i w t)) V^dagger.
+    The exact propagator of Eq. 2 that a Trotter product approximates (for
+    small n: the matrix is 2^n x 2^n)."""
+    w, V = np.linalg.eigh(Hd)
+    return (V * np.exp(-1j * t * w)) @ V.conj().T
+
+
 def apply_pauli(term: Term, psi: np.ndarray) -> np.ndarray:
     """Return P psi for a state (or a [.., N] batch) using the mask form."""
     N = psi.shape[-1]

@@ -312,3 +312,61 @@ def test_higher_order_error_scaling(oracle_lib, order, ratio, rs):
     terms, part = _setup(H, 8, t / rs[-1])
     e1 = np.linalg.norm(oev.evolve(terms, part, psi0, n, t / rs[-1], rs[-1]) - exact)
     assert errs[-1] < e1 / 10
+
+
+# ------------------------------------------------------------------ exact e^{-iHt} by eigendecomposition (n = 10)
+
+def test_eigh_propagator_is_unitary_and_agrees_with_expm():
+    """The eigendecomposition reference against an independent routine
+    (scipy's Pade scaling-and-squaring) and unitarity."""
+    n = 6
+    H = wh.heisenberg_1d(n, 1.0, fields=np.linspace(-0.8, 0.6, n))
+    Hd = pauli.dense_hamiltonian(pauli.parse_terms(H.strings, H.coeffs, n), n)
+    U = pauli.dense_propagator(Hd, 0.7)
+    assert np.abs(U - sl.expm(-0.7j * Hd)).max() < 1e-12
+    assert np.abs(U.conj().T @ U - np.eye(1 << n)).max() < 1e-12
+
+
+def test_commuting_hamiltonian_matches_eigh_propagator_n10(oracle_lib):
+    """Disjoint Heisenberg bonds with equal Z fields on both qubits of a bond:
+    every term commutes with D's fields and with the other bonds, so the
+    Trotter product is exact for any r (Eq. 4 with commuting H_j equals Eq. 2)."""
+    n, t = 10, 0.9
+    terms_s = []
+    for b in range(n // 2):
+        i = 2 * b
+        for p in "XYZ":
+            s = ["I"] * n
+            s[i] = s[i + 1] = p
+            terms_s.append(("".join(s), 0.7 + 0.1 * b))
+        hb = -0.5 + 0.3 * b
+        for q in (i, i + 1):
+            s = ["I"] * n
+            s[q] = "Z"
+            terms_s.append(("".join(s), hb))
+    H = wh.Hamiltonian(n, terms_s)
+    Hd = pauli.dense_hamiltonian(pauli.parse_terms(H.strings, H.coeffs, n), n)
+    psi0 = _rand_state(n, 21)
+    exact = pauli.dense_propagator(Hd, t) @ psi0
+    for r in (1, 3, 8):
+        terms, part = _setup(H, 16, t / r)
+        assert len(part.groups) >= 2
+        assert np.abs(oev.evolve(terms, part, psi0, n, t / r, r) - exact).max() < 1e-12
+
+
+@pytest.mark.parametrize("name", ["tfim", "heis"])
+def test_first_order_converges_to_eigh_propagator_n10(oracle_lib, name):
+    """n = 10: the oracle's product against exp(-iHt) from the dense
+    eigendecomposition: global error ratio 2 per doubling of r (first order)."""
+    n, t = 10, 1.0
+    H = wh.tfim_1d(n, 1.0, 1.0) if name == "tfim" else _heis(n)
+    Hd = pauli.dense_hamiltonian(pauli.parse_terms(H.strings, H.coeffs, n), n)
+    psi0 = _rand_state(n, 31)
+    exact = pauli.dense_propagator(Hd, t) @ psi0
+    errs = []
+    for r in (32, 64, 128, 256):
+        terms, part = _setup(H, 16, t / r)
+        errs.append(np.linalg.norm(oev.evolve(terms, part, psi0, n, t / r, r) - exact))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(1.85 < q < 2.15 for q in ratios), ratios
+    assert errs[-1] < 0.05
