@@ -74,3 +74,75 @@ def test_failing_job_is_isolated():
     status = {r.job_id: r.status for r in res}
     assert status[99] in ("error", "rejected")
     assert all(status[j.job_id] == "ok" for j in jobs)
+
+
+def test_running_job_is_cancelled_at_a_chunk_boundary():
+    hs, torch = hs_gpu()
+    from paper_2606_16959_amd.serve import Server
+    jobs = [j for _, j in _jobs(3, keep=False)]
+    target = jobs[1]
+    target.steps, target.chunk_steps = 40, 5
+
+    class CancelAfterFirstChunk(Server):
+        def _evolve_chunk(self, f, psi, steps, job, stream):
+            super()._evolve_chunk(f, psi, steps, job, stream)
+            if job.job_id == target.job_id:
+                self.cancel(job.job_id)
+    note("serve: cancel a running job after its first chunk")
+    res, st = CancelAfterFirstChunk(slots=2).run(jobs)
+    by = {r.job_id: r for r in res}
+    assert by[target.job_id].status == "cancelled" and by[target.job_id].steps_done == 5
+    assert all(by[j.job_id].status == "ok" for j in jobs if j is not target)
+
+
+def test_injected_fault_after_k_steps_leaves_other_jobs_bitwise_unchanged():
+    hs, torch = hs_gpu()
+    from paper_2606_16959_amd.serve import Server
+    pairs = _jobs(4, n_max=13)
+    jobs = [j for _, j in pairs]
+    for j in jobs:
+        j.chunk_steps = 7
+    victim = jobs[2].job_id
+
+    class FaultAfterK(Server):
+        victim_steps = 0                    # only the victim's worker thread touches it
+
+        def _evolve_chunk(self, f, psi, steps, job, stream):
+            if job.job_id == victim and self.victim_steps >= 14:
+                raise RuntimeError("injected fault")
+            super()._evolve_chunk(f, psi, steps, job, stream)
+            if job.job_id == victim:
+                self.victim_steps += steps
+    note("serve: injected fault in one job after 14 steps")
+    res, st = FaultAfterK(slots=4).run(jobs)
+    by = {r.job_id: r for r in res}
+    assert by[victim].status == "error" and "injected fault" in by[victim].error
+    assert by[victim].steps_done == 14
+    note("serve: the other jobs alone")
+    for j in jobs:
+        if j.job_id == victim:
+            continue
+        alone, _ = Server(slots=1).run([j], realtime=False)
+        assert by[j.job_id].status == "ok"
+        assert np.array_equal(alone[0].psi, by[j.job_id].psi), j.job_id
+
+
+def test_footprint_uses_the_jobs_dtype():
+    hs, torch = hs_gpu()
+    from paper_2606_16959_amd.serve import Server
+    from workloads import hamiltonians as wh
+    # a coupling range of 13 bits: closed in a complex64 tile of 8192 rows,
+    # open (scratch state) in complex128, whose tiles hold 4096 rows; n = 21
+    # keeps 256 full-size tiles, so the planner does not shrink them
+    n = 21
+    strings = ["X" + "I" * 11 + "X" + "I" * (n - 13), "Z" * n]
+    from paper_2606_16959_amd.serve import Job
+    j64 = Job(0, strings, np.array([0.3, 0.2]), n, 1.0, 4, 2, 0, budget=16, dtype="c64")
+    j128 = Job(1, strings, np.array([0.3, 0.2]), n, 1.0, 4, 2, 0, budget=16, dtype="c128")
+    s = Server(slots=1)
+    fp64, fp128 = s.footprint(j64), s.footprint(j128)
+    for j, fp in ((j64, fp64), (j128, fp128)):
+        f = hs.build_factors(j.strings, j.coeffs, n, 1.0, 4, 16, dtype=j.dtype)
+        assert fp == f.footprint(j.batch)
+        f.close()
+    assert fp128 - 2 * fp64 > (1 << n) * 16      # the complex128 scratch state

@@ -83,7 +83,49 @@ def test_oversize_job_is_rejected_others_complete():
 def test_summary_fields():
     s = FakeServer({j: 1 for j in range(5)}, {j: 0.002 for j in range(5)}, slots=2, hbm_budget=4)
     res, st = s.run(_jobs(5, 0.001))
-    for key in ("latency_ms", "queue_wait_ms", "service_ms", "throughput_jobs_s", "gpu_busy_frac"):
+    for key in ("latency_ms", "queue_wait_ms", "service_ms", "throughput_jobs_s", "device_busy_frac"):
         assert key in st
     assert st["latency_ms"]["p99"] >= st["latency_ms"]["p50"] > 0
     assert summarize([])["completed"] == 0
+
+
+def test_queued_job_is_cancelled_others_complete(tmp_path):
+    # one slot: job 0 runs while 1..4 wait; cancelling 2 removes it from the queue
+    sizes = {j: 1 for j in range(5)}
+    s = FakeServer(sizes, {j: 0.05 for j in range(5)}, slots=1, hbm_budget=10)
+    s.cancel(2)
+    path = tmp_path / "jobs.jsonl"
+    res, st = s.run(_jobs(5), jsonl=str(path))
+    status = {r.job_id: r.status for r in res}
+    assert status == {0: "ok", 1: "ok", 2: "cancelled", 3: "ok", 4: "ok"}
+    assert 2 not in s.order
+    assert st["completed"] == 4 and st["cancelled"] == 1
+
+
+def test_jsonl_has_one_record_per_job_with_final_status(tmp_path):
+    import json
+    sizes = {0: 1, 1: 99, 2: 1, 3: 2}
+    s = FakeServer(sizes, {j: 0.002 for j in range(4)}, slots=2, hbm_budget=10)
+    s.cancel(3)
+    path = tmp_path / "jobs.jsonl"
+    res, st = s.run(_jobs(4, 0.001), jsonl=str(path))
+    recs = [json.loads(line) for line in path.read_text().splitlines()]
+    assert sorted(r["job_id"] for r in recs) == [0, 1, 2, 3]
+    by = {r["job_id"]: r for r in recs}
+    assert by[0]["status"] == "ok" and by[2]["status"] == "ok"
+    assert by[1]["status"] == "rejected" and by[3]["status"] == "cancelled"
+    for r in (by[0], by[2]):
+        assert r["latency_ms"] >= r["service_ms"] >= 0 and r["queue_wait_ms"] >= 0
+        assert r["footprint_bytes"] == sizes[r["job_id"]]
+
+
+def test_invalid_job_fails_alone():
+    class Bad(FakeServer):
+        def footprint(self, job):
+            if job.job_id == 1:
+                raise ValueError("bad Hamiltonian")
+            return super().footprint(job)
+    s = Bad({j: 1 for j in range(3)}, {j: 0.001 for j in range(3)}, slots=2, hbm_budget=10)
+    res, st = s.run(_jobs(3))
+    assert [r.status for r in res] == ["ok", "error", "ok"]
+    assert "bad Hamiltonian" in res[1].error
