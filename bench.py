@@ -138,14 +138,13 @@ def cpu_baseline(H, psi0_c64, budget, t, steps_total, sample_steps, step_bytes):
     t0 = time.perf_counter()
     oev.evolve(terms, part, psi, H.n, t / steps_total, 0)          # setup only (phase table)
     t1 = time.perf_counter()
-    oev.evolve(terms, part, psi, H.n, t / steps_total, sample_steps)
+    ref = oev.evolve(terms, part, psi, H.n, t / steps_total, sample_steps)
     t2 = time.perf_counter()
     per_step = ((t2 - t1) - (t1 - t0)) / sample_steps
-    ref = oev.evolve(terms, part, psi, H.n, t / steps_total, sample_steps)
     return {
         "value": round(step_bytes / per_step / 1e9, 3), "unit": "GB/s",
         "cores": threads, "kind": "oracle",
-        "sample": f"{sample_steps} Trotter steps of the same n=26 workload, full state, FP64 "
+        "sample": f"{sample_steps} Trotter steps of the same n=26 workload (its whole run when 50), full state, FP64 "
                   f"(C + OpenMP, {threads} threads); setup (phase table, {t1 - t0:.2f} s) excluded; "
                   f"value = the step's algorithmic DIA bytes / oracle step time",
         "ms_per_step": round(per_step * 1e3, 1),
@@ -165,7 +164,8 @@ def accuracy(got, ref):
 def serve_leg(torch, n_jobs, rate, slots, oracle_nmax):
     """Served stream (seeded Poisson arrivals of mixed-family jobs) and the
     oracle check of a 5% sample (jobs whose id hashes into the sample and
-    whose n <= oracle_nmax; state column 0)."""
+    whose n <= oracle_nmax, every n by default; state column 0, the whole run
+    of the job, after the stream)."""
     from oracle import evolve as oev, factors as ofac, metrics, pauli as opauli
     from paper_2606_16959_amd.serve import Job, Server
     from workloads.serve_stream import job_stream
@@ -182,7 +182,7 @@ def serve_leg(torch, n_jobs, rate, slots, oracle_nmax):
     res, st = Server(slots=slots).run(jobs)
     log(f"serve: p50 {st['latency_ms']['p50']:.1f} ms p99 {st['latency_ms']['p99']:.1f} ms "
         f"{st['throughput_jobs_s']:.1f} jobs/s")
-    worst, checked = 1.0, 0
+    worst, checked, t_or = 1.0, 0, time.perf_counter()
     for sp, job, r in zip(specs, jobs, res):
         if not job.keep_result or r.status != "ok":
             continue
@@ -192,8 +192,11 @@ def serve_leg(torch, n_jobs, rate, slots, oracle_nmax):
         ref = oev.evolve(terms, part, r.psi0[0].astype(np.complex128), H.n, job.t / job.steps, job.steps)
         worst = min(worst, float(metrics.fidelity(r.psi[0].astype(np.complex128), ref)))
         checked += 1
-    st.update(jobs=n_jobs, rate_jobs_s=rate, oracle_sample=len(sample), oracle_checked=checked,
-              oracle_min_fidelity=worst, families="tfim/heisenberg/maxcut/tsp", n_range=[10, 24])
+    sampled = sum(1 for sp in specs if sp.job_id in sample and sp.n <= oracle_nmax)
+    log(f"serve: oracle checked {checked} of {sampled} sampled jobs in {time.perf_counter() - t_or:.1f} s")
+    st.update(jobs=n_jobs, rate_jobs_s=rate, oracle_sample=len(sample), oracle_sampled_checkable=sampled,
+              oracle_checked=checked, oracle_min_fidelity=worst, oracle_nmax=oracle_nmax,
+              families="tfim/heisenberg/maxcut/tsp", n_range=[10, 24])
     return st
 
 
@@ -347,14 +350,17 @@ def sweep(torch, steps, warmup, passes=3):
     print("\n".join(md))
 
 
-# steps checked against the oracle: whole runs for the n = 8 and n = 20 chains, 2 at n = 24 (8 states)
-ACCURACY_STEPS = {"tfim_chain_n8": 10, "heisenberg_chain_n20": 100, "maxcut_3reg_n24": 2}
+# steps checked against the oracle: the whole stated run of each workload
+ACCURACY_STEPS = {"tfim_chain_n8": 10, "heisenberg_chain_n20": 100, "maxcut_3reg_n24": 200}
+BACKGROUND_ORACLE = {"maxcut_3reg_n24"}    # its 8 x 200 oracle steps run beside the GPU-only legs
 
 
-def other_workloads(torch, steps=10, warmup=2):
+def other_workloads(torch, steps=10, warmup=2, pool=None):
     """The other named workloads in the same harness: per-step time
     and algorithmic GB/s (n <= 20 states stay in the 256 MB last-level cache,
-    so only n = 24 and n = 26 figures are HBM-bound)."""
+    so only n = 24 and n = 26 figures are HBM-bound).  With `pool`, the
+    long oracle runs are submitted there; the row's "accuracy_vs_oracle" is
+    then a future, resolved by resolve_pending()."""
     import paper_2606_16959_amd as hs
     from workloads import workload_hamiltonian, states as ws
     from workloads.hamiltonians import WORKLOAD_RUN
@@ -394,14 +400,20 @@ def other_workloads(torch, steps=10, warmup=2):
             # workload's initial states (complex64 also against complex128)
             k = ACCURACY_STEPS[cfg]
             psi0 = np.ascontiguousarray(ws.workload_states(cfg, np.complex128))
-            if cfg not in oracle_refs:
-                terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
-                part = ofac.first_fit(terms, run["budget"], run["t"] / run["steps"])
-                oracle_refs[cfg] = oev.evolve(terms, part, psi0, H.n, run["t"] / run["steps"], k)
             pa = torch.from_numpy(psi0.astype(npd)).cuda()
             hs.evolve(f, pa, k)
             got = pa.cpu().numpy()
-            row["accuracy_vs_oracle"] = dict(accuracy(got, oracle_refs[cfg]), steps=k)
+            terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
+            part = ofac.first_fit(terms, run["budget"], run["t"] / run["steps"])
+            job = (lambda terms=terms, part=part, psi0=psi0, n=H.n, dt=run["t"] / run["steps"], k=k:
+                   oev.evolve(terms, part, psi0, n, dt, k))
+            if pool is not None and cfg in BACKGROUND_ORACLE:
+                fut = pool.submit(job)
+                row["accuracy_vs_oracle"] = ("pending", fut, got, k)
+            else:
+                if cfg not in oracle_refs:
+                    oracle_refs[cfg] = job()
+                row["accuracy_vs_oracle"] = dict(accuracy(got, oracle_refs[cfg]), steps=k)
             if dtype == "c128":
                 c128_states[cfg] = got
             elif cfg in c128_states:
@@ -412,6 +424,102 @@ def other_workloads(torch, steps=10, warmup=2):
         f.close()
         del psi
         torch.cuda.empty_cache()
+    return out
+
+
+def resolve_pending(rows):
+    """Wait for background oracle runs and fill in their accuracy."""
+    for row in rows:
+        acc = row.get("accuracy_vs_oracle")
+        if isinstance(acc, tuple) and acc and acc[0] == "pending":
+            _, fut, got, k = acc
+            t0 = time.perf_counter()
+            row["accuracy_vs_oracle"] = dict(accuracy(got, fut.result()), steps=k, states=int(got.shape[0]))
+            log(f"{row['workload']} vs oracle ({k} steps, waited {time.perf_counter() - t0:.1f} s): "
+                f"{row['accuracy_vs_oracle']}")
+    return rows
+
+
+def complex128_leg(torch, H, psi0, ref, ref_steps, state_c64, steps_total, budget, timed=10, warmup=2):
+    """The plain complex128 path on the headline workload: per-step time and
+    algorithmic GB/s of its own launches, and the whole run's error against
+    the FP64 oracle (ref, after ref_steps steps) and against the complex64
+    GPU state after the same steps."""
+    import paper_2606_16959_amd as hs
+    N = 1 << H.n
+    f = hs.build_factors(H.strings, H.coeffs, H.n, 1.0, steps_total, budget, dtype="c128")
+    launches = f.step_launches(1)
+    per = launch_bytes(f.describe(), launches, N, 1, 16)
+    psi = torch.from_numpy(psi0.astype(np.complex128)).cuda()
+    hs.evolve(f, psi, warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(timed):
+        hs.evolve(f, psi, 1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / timed
+    k = ref_steps
+    psi.copy_(torch.from_numpy(psi0.astype(np.complex128)))
+    hs.evolve(f, psi, k)
+    got = psi.cpu().numpy()
+    f.close()
+    del psi
+    torch.cuda.empty_cache()
+    gbs = sum(per) / ms / 1e6
+    out = {"workload": "tfim2d_5x5_plus_idle_ancilla", "n": H.n, "dtype": "c128", "batch": 1,
+           "launches_per_step": len(launches), "ms_per_step": round(ms, 4),
+           "gb_per_step": round(sum(per) / 1e9, 3), "gbs": round(gbs, 1),
+           "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+           "accuracy_vs_oracle": dict(accuracy(got, ref), steps=k),
+           "fidelity_c64_vs_c128": accuracy(state_c64, got)["min_fidelity"]}
+    log(f"complex128 n=26: {ms:.3f} ms/step {out['gbs']} GB/s; vs oracle {out['accuracy_vs_oracle']}; "
+        f"c64 vs c128 fidelity {out['fidelity_c64_vs_c128']}")
+    return out
+
+
+def diagonal_leg(torch, n=26, steps=200, timed=10, seed=26):
+    """Diagonal-only Hamiltonian (the MaxCut cost of a seeded 3-regular graph,
+    no mixer, n = 26, complex64, t = 1): one step is the single-diagonal
+    factor exp(-i dt E).  Timed step by step (one pass per step) and as the
+    whole run in one pass (the library applies all steps of a diagonal step
+    per entry in registers).  Algorithmic bytes per pass: the diagonal once,
+    the state read and written: 3 N 8."""
+    import paper_2606_16959_amd as hs
+    from workloads import hamiltonians as wh, states as ws
+    rng = np.random.Generator(np.random.PCG64(seed))
+    edges = wh.random_regular_graph(n, 3, rng)
+    H = wh.maxcut(n, edges, rng.uniform(1.0, 10.0, len(edges)), mixer=0.0)
+    N = 1 << n
+    f = hs.build_factors(H.strings, H.coeffs, n, 1.0, steps, 16, dtype="c64")
+    assert f.n_factors == 1
+    psi = torch.from_numpy(ws.random_phase_state(n, 5, np.complex64)).cuda()
+    nbytes = 3 * N * 8
+    hs.evolve(f, psi, 1)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    for _ in range(timed):
+        hs.evolve(f, psi, 1)
+    e1.record()
+    hs.evolve(f, psi, steps)
+    e2.record()
+    torch.cuda.synchronize()
+    ms1 = e0.elapsed_time(e1) / timed
+    msr = e1.elapsed_time(e2)
+    f.close()
+    del psi
+    torch.cuda.empty_cache()
+    out = {"workload": f"maxcut_cost_3reg_n{n}_no_mixer", "n": n, "dtype": "c64", "batch": 1,
+           "gb_per_pass": round(nbytes / 1e9, 3),
+           "one_step_per_pass": {"ms_per_step": round(ms1, 4), "gbs": round(nbytes / ms1 / 1e6, 1),
+                                 "frac_of_peak": round(nbytes / ms1 / 1e6 / HBM_PEAK_GBS, 4)},
+           "all_steps_one_pass": {"steps": steps, "ms": round(msr, 4), "ms_per_step": round(msr / steps, 5),
+                                  "gbs": round(nbytes / msr / 1e6, 1),
+                                  "frac_of_peak": round(nbytes / msr / 1e6 / HBM_PEAK_GBS, 4)}}
+    log(f"diagonal n={n}: {ms1:.4f} ms/step ({out['one_step_per_pass']['gbs']} GB/s); "
+        f"{steps} steps in one pass {msr:.3f} ms ({out['all_steps_one_pass']['gbs']} GB/s)")
     return out
 
 
@@ -511,6 +619,125 @@ def taylor_leg(torch, cases=None, timed_steps=3):
     return out
 
 
+def one_workload_leg(torch, name, dtype, steps=5, warmup=2, batch=None):
+    """One named workload alone (for profiling): `warmup` + `steps` Trotter
+    steps of its states, then one 2 GiB device copy that calibrates the HBM
+    counters.  Reports the launches of one step with their algorithmic bytes,
+    so a counter summary can be set against them."""
+    import paper_2606_16959_amd as hs
+    from workloads import workload_hamiltonian, states as ws
+    from workloads.hamiltonians import WORKLOAD_RUN
+    H = workload_hamiltonian(name)
+    run = WORKLOAD_RUN[name]
+    npd = np.complex128 if dtype == "c128" else np.complex64
+    elem = 16 if dtype == "c128" else 8
+    B = batch or run["batch"]
+    f = hs.build_factors(H.strings, H.coeffs, H.n, run["t"], run["steps"], run["budget"], dtype=dtype)
+    launches = f.step_launches(B)
+    per = launch_bytes(f.describe(), launches, 1 << H.n, B, elem)
+    states = ws.workload_states(name, npd)
+    psi = torch.from_numpy(np.ascontiguousarray(np.resize(states, (B, states.shape[1])))).cuda()
+    hs.evolve(f, psi, warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    hs.evolve(f, psi, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    f.close()
+    del psi
+    torch.cuda.empty_cache()
+    copy_bandwidth(torch, reps=1)
+    return {"workload": name, "n": H.n, "dtype": dtype, "batch": B, "warmup": warmup, "steps": steps,
+            "launches_per_step": len(launches), "launch_factors": [c for _, c in launches],
+            "algorithmic_bytes_per_launch": [int(b) for b in per], "ms_per_step": round(ms, 4),
+            "gb_per_step": round(sum(per) / 1e9, 3), "gbs": round(sum(per) / ms / 1e6, 1),
+            "frac_of_peak": round(sum(per) / ms / 1e6 / HBM_PEAK_GBS, 4)}
+
+
+def _csv_rows(d, pattern):
+    import csv
+    import glob
+    out = []
+    for fn in sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True)):
+        with open(fn) as fh:
+            out += list(csv.DictReader(fh))
+    return out
+
+
+def summarize_leg_profiles(leg_output, trace_dir, counter_dirs, out_name, command):
+    """Per-launch summary of the DIA tile kernel from rocprofv3 output of a
+    `bench.py --leg workload` run: durations from the kernel trace, and from
+    each counter run (one directory per pass) the per-dispatch counter values,
+    averaged per launch position of a step.  FETCH_SIZE and WRITE_SIZE (KiB)
+    are scaled by what the same counters read for the leg's 2 GiB device copy
+    and set against the launch's algorithmic bytes."""
+    leg = None
+    with open(leg_output) as fh:
+        for line in fh:
+            if line.startswith('{"leg"'):
+                leg = json.loads(line)["result"]
+                break
+    if leg is None:
+        raise SystemExit(f"no leg output in {leg_output}")
+    L = leg["launches_per_step"]
+    alg = leg["algorithmic_bytes_per_launch"]
+    trace = sorted((r for r in _csv_rows(trace_dir, "*kernel_trace.csv") if "dia_tile_kernel" in r["Kernel_Name"]),
+                   key=lambda r: int(r["Dispatch_Id"]))
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in trace]
+    if len(durs) % L:
+        raise SystemExit(f"{len(durs)} tile dispatches is not a multiple of {L} launches per step")
+    pos_ms = [float(np.mean(durs[j::L])) for j in range(L)]
+    counters = {}                      # name -> [per tile dispatch], plus the copy's value
+    copy_val = {}
+    for d in counter_dirs:
+        rows = sorted(_csv_rows(d, "*counter_collection.csv"), key=lambda r: int(r["Dispatch_Id"]))
+        for name in sorted({r["Counter_Name"] for r in rows}):
+            mine = [r for r in rows if r["Counter_Name"] == name]
+            counters[name] = [float(r["Counter_Value"]) for r in mine if "dia_tile_kernel" in r["Kernel_Name"]]
+            cp = [float(r["Counter_Value"]) for r in mine if "copyBuffer" in r["Kernel_Name"]]
+            if cp:
+                copy_val[name] = max(cp)
+    copy_kib = (1 << 31) / 1024.0
+    md = [f"# dia_tile_kernel: {leg['workload']}, n={leg['n']}, {leg['dtype']}, {leg['batch']} state(s) per launch", "",
+          "Command (repository root, on the MI355X):", "", "```", command, "```", "",
+          f"Leg: {leg['warmup']} warm-up + {leg['steps']} timed Trotter steps; {L} launches per step "
+          f"(factors per launch {leg['launch_factors']}); {leg['ms_per_step']} ms/step from HIP events, "
+          f"{leg['gb_per_step']} algorithmic GB/step, {leg['gbs']} GB/s = {100 * leg['frac_of_peak']:.1f}% of 8 TB/s.", ""]
+    hdr = ["launch", "avg ms (trace)", "algorithmic GB", "algorithmic GB/s"]
+    scaled = {}
+    for cname in ("FETCH_SIZE", "WRITE_SIZE"):
+        if cname in counters and copy_val.get(cname):
+            scaled[cname] = copy_kib / copy_val[cname]
+    if scaled:
+        md += ["Copy calibration (2 GiB device copy in the same run): " +
+               ", ".join(f"{c} reads {copy_val[c]:.0f} KiB, scale {s:.4f}" for c, s in scaled.items()), ""]
+        hdr += ["HBM GB (scaled FETCH + WRITE)", "HBM / algorithmic"]
+    other = [c for c in sorted(counters) if c not in ("FETCH_SIZE", "WRITE_SIZE")]
+    hdr += other
+    md += ["| " + " | ".join(hdr) + " |", "|" + "---|" * len(hdr)]
+    for j in range(L):
+        row = [str(j), f"{pos_ms[j]:.4f}", f"{alg[j] / 1e9:.3f}", f"{alg[j] / pos_ms[j] / 1e6:.0f}"]
+        if scaled:
+            hb = sum(float(np.mean(counters[c][j::L])) * s * 1024 for c, s in scaled.items())
+            row += [f"{hb / 1e9:.3f}", f"{hb / alg[j]:.3f}"]
+        for c in other:
+            v = counters[c][j::L]
+            row.append(f"{float(np.mean(v)):.4g}" if v else "-")
+        md.append("| " + " | ".join(row) + " |")
+    stats = _csv_rows(trace_dir, "*kernel_stats.csv")
+    md += ["", "## rocprofv3 --kernel-trace --stats", "",
+           "| kernel | calls | avg us | min us | max us | % |", "|---|---|---|---|---|---|"]
+    for r in stats[:6]:
+        md.append(f"| {r['Name'][:95]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                  f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    os.makedirs(OUT_DIR, exist_ok=True)
+    with open(os.path.join(OUT_DIR, out_name), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 def _template_args(kernel_name):
     """Template arguments of a kernel name as printed by rocprofv3."""
     inner = kernel_name[kernel_name.index("<") + 1:kernel_name.rindex(">")]
@@ -604,13 +831,13 @@ def write_serve_summary(stats, command, fname):
           "admission; service = admission -> completion (factor build + state setup + evolution). "
           "Oracle check: jobs hashed into a 5% sample with n <= 16, state column 0, FP64 oracle.", "",
           "| jobs | rate (jobs/s) | completed | p50 ms | p99 ms | max ms | queue p50 ms | service p50 ms | "
-          "service p99 ms | throughput jobs/s | GPU busy | peak active | oracle checked | min fidelity |",
+          "service p99 ms | throughput jobs/s | device busy | peak active | oracle checked | min fidelity |",
           "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
     for st in stats:
         L, Q, S = st["latency_ms"], st["queue_wait_ms"], st["service_ms"]
         md.append(f"| {st['jobs']} | {st['rate_jobs_s']:g} | {st['completed']} | {L['p50']:.1f} | {L['p99']:.1f} | "
                   f"{L['max']:.1f} | {Q['p50']:.1f} | {S['p50']:.1f} | {S['p99']:.1f} | "
-                  f"{st['throughput_jobs_s']:.2f} | {st['gpu_busy_frac']:.3f} | {st['peak_active']} | "
+                  f"{st['throughput_jobs_s']:.2f} | {st['device_busy_frac'] or 0:.3f} | {st['peak_active']} | "
                   f"{st['oracle_checked']} | {st['oracle_min_fidelity']:.12f} |")
     with open(os.path.join(OUT_DIR, fname), "w") as fh:
         fh.write("\n".join(md) + "\n")
@@ -667,15 +894,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-fuse", action="store_true", help="one launch per factor")
     ap.add_argument("--renorm", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=8, help="oracle sample size (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=50, help="oracle sample size (0 = skip); 50 = the whole run")
     ap.add_argument("--no-copy-ref", action="store_true")
-    ap.add_argument("--serve-jobs", type=int, default=300, help="served-stream size (0 = skip)")
+    ap.add_argument("--serve-jobs", type=int, default=2000, help="served-stream size (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-slots", type=int, default=4)
-    ap.add_argument("--serve-oracle-nmax", type=int, default=16)
+    ap.add_argument("--serve-oracle-nmax", type=int, default=30, help="largest n of the checked sample")
     ap.add_argument("--serve-only", action="store_true", help="only the served stream")
-    ap.add_argument("--leg", choices=["taylor", "higher_order", "single_propagator", "other_workloads"],
+    ap.add_argument("--leg", choices=["taylor", "higher_order", "single_propagator", "other_workloads", "workload",
+                                      "diagonal"],
                     help="run one secondary leg alone and print its JSON (for profiling)")
+    ap.add_argument("--workload", default="maxcut_3reg_n24", help="named workload of --leg workload")
+    ap.add_argument("--dtype", default="c64", choices=["c64", "c128"], help="dtype of --leg workload")
+    ap.add_argument("--batch", type=int, default=0, help="states of --leg workload (0 = the workload's)")
+    ap.add_argument("--summarize-leg-profiles", nargs="+", metavar="DIR",
+                    help="LEG_OUTPUT TRACE COUNTER_DIR... : per-launch summary of a --leg workload run")
+    ap.add_argument("--summary-name", default="", help="file name under profiles/ of --summarize-leg-profiles")
     ap.add_argument("--no-other-workloads", action="store_true")
     ap.add_argument("--serve-sweep", default="", help="comma-separated arrival rates (jobs/s)")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
@@ -696,6 +930,10 @@ def main():
     if args.summarize_taylor_profiles:
         summarize_taylor_profiles(*args.summarize_taylor_profiles)
         return
+    if args.summarize_leg_profiles:
+        lo, tr, *cdirs = args.summarize_leg_profiles
+        summarize_leg_profiles(lo, tr, cdirs, args.summary_name or "leg_profile.md", args.profile_command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -711,7 +949,10 @@ def main():
         return
     if args.leg:
         legs = {"taylor": taylor_leg, "higher_order": higher_order_leg,
-                "single_propagator": single_propagator_leg, "other_workloads": other_workloads}
+                "single_propagator": single_propagator_leg, "other_workloads": other_workloads,
+                "workload": lambda tc: one_workload_leg(tc, args.workload, args.dtype, steps=args.steps,
+                                                        warmup=args.warmup, batch=args.batch or None),
+                "diagonal": diagonal_leg}
         print(json.dumps({"leg": args.leg, "result": legs[args.leg](torch)}), flush=True)
         return
     if args.serve_only:
@@ -789,6 +1030,7 @@ def main():
         log(f"device copy {cb:.1f} GB/s")
 
     cpu = None
+    ref = got64 = None
     if args.cpu_steps > 0:
         log(f"oracle sample: {args.cpu_steps} steps at n=26 on the host")
         cpu, ref = cpu_baseline(H, psi0, budget, t, steps_total, args.cpu_steps, step_bytes)
@@ -796,18 +1038,27 @@ def main():
         # the same steps on the GPU from the same state: error against the oracle
         pa = torch.from_numpy(psi0.copy()).cuda()
         hs.evolve(f, pa, args.cpu_steps, renorm=args.renorm, fuse=not args.no_fuse)
-        extra["accuracy_vs_oracle"] = dict(accuracy(pa.cpu().numpy(), ref), steps=args.cpu_steps)
+        got64 = pa.cpu().numpy()
+        extra["accuracy_vs_oracle"] = dict(accuracy(got64, ref), steps=args.cpu_steps)
         log(f"vs oracle after {args.cpu_steps} steps: {extra['accuracy_vs_oracle']}")
-        del pa, ref
+        del pa
 
     others = None
     if not args.no_other_workloads:
+        from concurrent.futures import ThreadPoolExecutor
         f.close()
         torch.cuda.empty_cache()
-        others = other_workloads(torch)
+        if ref is not None and not args.renorm:
+            extra["complex128"] = complex128_leg(torch, H, psi0, ref, args.cpu_steps, got64, steps_total, budget)
+        ref = got64 = None
+        pool = ThreadPoolExecutor(max_workers=1)      # long oracle runs beside the GPU-only legs
+        others = other_workloads(torch, pool=pool)
+        extra["diagonal_only"] = diagonal_leg(torch)
         others.append({"higher_order": higher_order_leg(torch)})
         others.append({"taylor_fused": taylor_leg(torch)})
         others.append({"single_propagator": single_propagator_leg(torch)})
+        resolve_pending(others)
+        pool.shutdown()
     serve = None
     if args.serve_jobs > 0:
         f.close()

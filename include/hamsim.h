@@ -23,7 +23,11 @@
  *  - State and diagonal pointers must be 16-byte aligned (HS_EINVAL otherwise).
  *  - Device pointers are HIP device addresses on the current device; a
  *    stream argument is a hipStream_t (NULL = the default stream).  All device
- *    work is enqueued on that stream.
+ *    work is enqueued on that stream.  Every call that takes caller states
+ *    or diagonals first checks that each is device (or managed) memory of the
+ *    current device and lies inside one allocation, and returns HS_EINVAL
+ *    before enqueuing anything otherwise: a host address must never reach a
+ *    kernel.
  *  - Every function returns an hs_status.  On failure nothing is left half
  *    built, output handles are set to NULL, and hs_last_error() returns a
  *    message for the calling thread.  No C++ exception crosses this ABI.
@@ -114,7 +118,8 @@ hs_status hs_build_factors(int n_qubits, int n_terms, const char *const *pauli_t
                            hs_dtype dtype, unsigned flags, void *stream, hs_factors *out);
 
 /*
- * hs_evolve -- psi <- (U_F ... U_1)^steps psi, in place, for `batch` states
+ * hs_evolve -- the repeat loop of Alg. 3 with the Trotter product of Eq. 4 as
+ * the step: psi <- (U_F ... U_1)^steps psi, in place, for `batch` states
  * (device pointer to [batch][N] interleaved complex of the factors' dtype).
  * Enqueues kernels on `stream` and returns; faults surface at the caller's
  * next synchronisation.  May be called repeatedly: for first order,
@@ -135,6 +140,8 @@ hs_status hs_build_factors(int n_qubits, int n_terms, const char *const *pauli_t
  * at large n) is applied out of place into a scratch state (allocated on
  * first use, counted by hs_footprint) and copied back.  Calls that share a
  * handle share its workspace, so they must be ordered on one stream.
+ * The state is checked (device memory, batch * N elements inside one
+ * allocation) before anything else, also when steps is 0.
  */
 hs_status hs_evolve(hs_factors f, void *psi, int batch, int steps, void *stream,
                     unsigned flags);
@@ -171,8 +178,17 @@ hs_status hs_factor_offsets(hs_factors f, int k, long long *offsets, int cap);
 hs_status hs_factor_copy_diagonal(hs_factors f, int k, int j, long long start, long long count,
                                   void *host_dst, void *stream);
 /* Bytes of device memory an evolution of `batch` states needs: the stored
- * diagonals, the caller's states and the library's workspace. */
+ * diagonals (Eq. 6: N - |d| entries per diagonal, each start aligned to 256
+ * bytes), the caller's states and the library's workspace (the scratch state
+ * of an open launch, reduction partials).  Used for admission by HBM
+ * footprint in a served loop.  Counts the handle's dtype (complex64 for a
+ * handle from hs_plan, which has none yet). */
 hs_status hs_footprint(hs_factors f, int batch, size_t *bytes);
+/* The same figure for the handle built with `dtype`: element size, diagonal
+ * alignment and the dtype's own tile limits (a complex128 tile holds half
+ * the rows, so a factor closed in complex64 can need the open launch and its
+ * scratch state in complex128).  For admission before building. */
+hs_status hs_footprint_dtype(hs_factors f, int batch, hs_dtype dtype, size_t *bytes);
 /* The launches one Trotter step makes for `batch` states with evolve `flags`:
  * *n_launches receives their count; launch i applies the factors at
  * positions [first_factor[i], first_factor[i] + n_factors[i]) of the part's
@@ -210,7 +226,10 @@ hs_status hs_dia_spmv(int n_diags, const long long *offsets, const void *const *
                       const void *x, void *y, int batch, long long N, hs_dtype dtype,
                       void *stream);
 
-/* FP64 squared norms of `batch` device states; out: host [batch]; syncs. */
+/* FP64 squared norms <psi|psi> of `batch` device states (the norm that the
+ * paper's Alg. 2 takes of its Taylor terms, here of states; the per-step
+ * renormalisation of hs_evolve uses the same FP64 accumulation); out: host
+ * [batch]; syncs. */
 hs_status hs_norm2(const void *psi, int batch, long long N, hs_dtype dtype, void *stream,
                    double *out);
 
@@ -287,7 +306,8 @@ hs_status hs_estimate_timesteps(hs_dia H, double t, int budget, double tol, int 
 hs_status hs_dia_to_c64(hs_dia A, void *stream, hs_dia *out);
 /* Alg. 3's loop: psi <- U^steps psi for `batch` device states of U's dtype,
  * by repeated DIA SpMV (out of place with library scratch, result written
- * back to psi).  Synchronises `stream`. */
+ * back to psi).  The state is checked before anything else, also when
+ * steps is 0.  Synchronises `stream`. */
 hs_status hs_dia_evolve(hs_dia U, void *psi, int batch, int steps, void *stream);
 /* nu(A) = sum over A's stored diagonals (ascending offset) of each one's
  * largest entry modulus; bounds ||A||_1, ||A||_inf and ||A||_2.  Syncs. */
@@ -313,6 +333,7 @@ hs_status hs_taylor_steps(hs_dia H, double t, double theta, void *stream, int *s
 /* psi <- p_K(-i dt H)^steps psi for `batch` device states ([batch][N], of
  * H's dtype, 16-byte aligned), 1 <= K <= 64.  In place; library scratch of
  * two states per chunk of HS_MAX_BATCH (one for K = 1), stream-ordered.
+ * The state is checked before anything else, also when steps is 0.
  * Synchronises `stream`. */
 hs_status hs_taylor_evolve(hs_dia H, void *psi, int batch, double dt, int K, int steps, void *stream);
 hs_status hs_dia_free(hs_dia A);

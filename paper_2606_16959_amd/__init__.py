@@ -146,9 +146,14 @@ class Factors:
             return seq[1:-1] + [j]
         return seq[1:]
 
-    def footprint(self, batch: int = 1) -> int:
+    def footprint(self, batch: int = 1, dtype=None) -> int:
+        """Device bytes an evolution of `batch` states needs (the handle's
+        dtype, or `dtype`: a planned handle has none yet)."""
         b = ctypes.c_size_t()
-        _lib.check(_lib.load().hs_footprint(self._h, batch, b))
+        if dtype is None:
+            _lib.check(_lib.load().hs_footprint(self._h, batch, b))
+        else:
+            _lib.check(_lib.load().hs_footprint_dtype(self._h, batch, dtype_code(dtype), b))
         return b.value
 
     def check_closure(self, stream=None) -> bool:
@@ -191,6 +196,11 @@ def build_factors(strings, coeffs, n, t, steps, budget, dtype="c64", merge_diag=
 
 
 def _state_args(psi, N=None):
+    if not getattr(psi, "is_cuda", False):
+        raise ValueError("state must be a tensor in device memory (a host tensor would fault the GPU)")
+    import torch
+    if psi.device.index != torch.cuda.current_device():
+        raise ValueError(f"state lives on {psi.device}, the current device is cuda:{torch.cuda.current_device()}")
     if not psi.is_contiguous():
         raise ValueError("state must be contiguous")
     batch = 1 if psi.dim() == 1 else psi.shape[0]
@@ -243,6 +253,10 @@ def dia_spmv(offsets, diags, x, y=None, stream=None):
     for d, v in zip(offsets, diags):
         if v.numel() != N - abs(int(d)) or dtype_code(v.dtype) != code:
             raise ValueError("diagonal length or dtype mismatch")
+        if not v.is_cuda or v.device != x.device:
+            raise ValueError("diagonals must be device tensors on the state's device")
+    if not y.is_cuda or y.device != x.device:
+        raise ValueError("y must be a device tensor on x's device")
     _lib.check(_lib.load().hs_dia_spmv(len(offsets), offs, ptrs, ctypes.c_void_p(x.data_ptr()),
                                        ctypes.c_void_p(y.data_ptr()), batch, N, code,
                                        _stream_ptr(stream)))

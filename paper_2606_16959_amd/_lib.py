@@ -39,6 +39,7 @@ _SIG = {
     "hs_step_launches": (_I, [_P, _I, ctypes.c_uint, _I, ctypes.POINTER(_I), _P, _P, _I]),
     "hs_step_joint": (_I, [_P, ctypes.POINTER(_I)]),
     "hs_footprint": (_I, [_P, _I, ctypes.POINTER(ctypes.c_size_t)]),
+    "hs_footprint_dtype": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_size_t)]),
     "hs_check": (_I, [_P, _P, ctypes.POINTER(_I)]),
     "hs_free_factors": (_I, [_P]),
     "hs_dia_spmv": (_I, [_I, _P, _P, _P, _P, _I, _LL, _I, _P]),

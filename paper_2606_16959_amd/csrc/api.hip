@@ -38,6 +38,42 @@ hs_status fail(hs_status s, const std::string &m) {
 
 namespace hs {
 void set_last_error(const std::string &m) { g_err = m; }
+
+bool device_range_ok(const void *p, size_t bytes, const char *what, std::string &msg) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        msg = std::string(what) + ": no current device";
+        return false;
+    }
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        msg = std::string(what) + " is not device memory (a host address?)";
+        return false;
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged) {
+        msg = std::string(what) + " is not device memory (a host address?)";
+        return false;
+    }
+    if (at.type == hipMemoryTypeDevice && at.device != dev) {
+        msg = std::string(what) + " lives on device " + std::to_string(at.device) + ", the current device is " +
+              std::to_string(dev);
+        return false;
+    }
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void *>(p)) == hipSuccess && base && size) {
+        const char *lo = static_cast<const char *>(base);
+        if (static_cast<const char *>(p) + bytes > lo + size) {
+            msg = std::string(what) + " extends past the end of its allocation";
+            return false;
+        }
+    } else {
+        (void)hipGetLastError();      // pool allocations may not report a range
+    }
+    return true;
+}
 }  // namespace hs
 
 namespace {
@@ -61,6 +97,9 @@ struct Run {
     bool elementwise = false;   // a single main-diagonal factor
     bool open = false;          // no closed tile holds the factor's coupling range: open
                                 // launch into the scratch state, then copied back
+    bool pairs = false;         // closed complex64 launch whose every diagonal pairs: the
+                                // partners of a thread's two rows are adjacent, even-aligned
+                                // LDS entries (regular offset, and W even or the offset even)
     int desc_start = 0;
     std::vector<int> dstart;    // per factor, relative to desc_start (size nf + 1)
 };
@@ -191,6 +230,7 @@ hs_status make_evolve_plan(hs_factors_s *h, const PlanKey &key, EvolvePlan &ep, 
             }
             run.desc_start = (int)ep.host_desc.size();
             run.dstart.push_back(0);
+            run.pairs = key.pairs && h->dtype == HS_C64 && !run.open && !run.elementwise;
             for (int k : run.factors) {
                 const Factor &Fk = P.factors[k];
                 for (size_t j = 0; j < Fk.offs.size(); ++j) {
@@ -203,6 +243,7 @@ hs_status make_evolve_plan(hs_factors_s *h, const PlanKey &key, EvolvePlan &ep, 
                     dd.m = dd.regular ? (int32_t)(d >> run.geo.qb) : 0;
                     dd.lo = (int32_t)std::max<int64_t>(0, -d);
                     dd.hi = (int32_t)std::min<int64_t>(P.N, P.N - d);
+                    if (!dd.regular || (run.geo.logW == 0 && (d & 1))) run.pairs = false;
                     ep.host_desc.push_back(dd);
                 }
                 run.dstart.push_back((int)(ep.host_desc.size() - run.desc_start));
@@ -237,7 +278,8 @@ hs_status launch_run(hs_factors_s *h, const EvolvePlan &ep, const Run &run, void
     const size_t sc = elem_bytes(h->dtype);
     if (run.elementwise) {
         const Factor &Fk = P.factors[run.factors[0]];
-        int e = hs::launch_diag_elementwise(psi, psi, Fk.dev, P.N, chunk, nrm2_records, c128, stream);
+        int e = hs::launch_diag_steps(psi, psi, Fk.dev, P.N, chunk, 1, nrm2_records, c128,
+                                      stream_out(chunk, P.N, h->dtype), stream);
         if (e) return hip_fail((hipError_t)e, "diag kernel launch");
         return HS_OK;
     }
@@ -261,6 +303,7 @@ hs_status launch_run(hs_factors_s *h, const EvolvePlan &ep, const Run &run, void
         a.viol = run.open ? nullptr : h->viol_dev;
         a.swizzle = swizzled(ep.swizzle, run.geo) ? 1 : 0;
         a.stream_out = stream_out(chunk, P.N, h->dtype);
+        a.pairs = run.pairs ? 1 : 0;
         // partials of state b0 + b at [((b0 + b) * tiles + tile) * 4]
         a.norm_out = norm_partials ? norm_partials + (size_t)b0 * (P.N / run.geo.T) * 4 : nullptr;
         const int nb = std::min(lbatch, chunk - b0);
@@ -439,10 +482,16 @@ hs_status hs_evolve(hs_factors f, void *psi, int batch, int steps, void *stream,
     if (steps < 0) return fail(HS_EINVAL, "steps must be >= 0");
     if (flags & ~(unsigned)(HS_RENORM | HS_NO_FUSE)) return fail(HS_EINVAL, "unknown evolve flag");
     if (reinterpret_cast<uintptr_t>(psi) % 16) return fail(HS_EINVAL, "state pointer must be 16-byte aligned");
-    if (steps == 0) return HS_OK;
-    std::lock_guard<std::mutex> lock(f->mu);
     const Plan &P = f->plan;
     const size_t sc = elem_bytes(f->dtype);
+    {
+        // checked before the zero-step return, so a caller can validate a
+        // state without enqueuing work
+        std::string msg;
+        if (!hs::device_range_ok(psi, (size_t)batch * P.N * sc, "state", msg)) return fail(HS_EINVAL, msg);
+    }
+    if (steps == 0) return HS_OK;
+    std::lock_guard<std::mutex> lock(f->mu);
     const bool fuse = !(flags & HS_NO_FUSE);
     const bool renorm = (flags & HS_RENORM) != 0;
     int cur_dev = 0;
@@ -485,6 +534,16 @@ hs_status hs_evolve(hs_factors f, void *psi, int batch, int steps, void *stream,
             }
         }
         void *p = static_cast<char *>(psi) + (size_t)c0 * P.N * sc;
+        const std::vector<Run> &lone = ep.runs[kPartLone];
+        if (!renorm && P.joint < 0 && lone.size() == 1 && lone[0].elementwise) {
+            // a step that is one diagonal factor: all steps in one pass (the
+            // same multiplications, one step after the other, per entry)
+            const Factor &Fk = P.factors[lone[0].factors[0]];
+            int e = hs::launch_diag_steps(p, p, Fk.dev, P.N, chunk, steps, nullptr, f->dtype == HS_C128,
+                                          stream_out(chunk, P.N, f->dtype), stream);
+            if (e) return hip_fail((hipError_t)e, "diag kernel launch");
+            continue;
+        }
         const double *rec = f->records() + 2;    // squared norm of state b at rec[4 b]
         for (int s = 0; s < steps; ++s) {
             const int part = steps == 1 ? kPartLone
@@ -645,29 +704,40 @@ hs_status hs_step_launches(hs_factors f, int batch, unsigned flags, int part, in
     return HS_OK;
 }
 
-hs_status hs_footprint(hs_factors f, int batch, size_t *bytes) {
-    if (hs_status s = check_handle(f)) return s;
-    if (batch < 1 || !bytes) return fail(HS_EINVAL, "batch >= 1 and an output are required");
-    const size_t sc = elem_bytes(f->dtype);
+static size_t footprint_bytes(const Plan &P, int dtype, int batch) {
+    const size_t sc = elem_bytes(dtype);
     size_t total = 0;
-    for (const auto &F : f->plan.factors) {
+    for (const auto &F : P.factors) {
         const size_t align = hs::kDiagAlignBytes / sc;
         for (int64_t d : F.offs) {
-            const size_t len = (size_t)(f->plan.N - (d < 0 ? -d : d));
+            const size_t len = (size_t)(P.N - (d < 0 ? -d : d));
             total += (len + align - 1) / align * align * sc;
         }
     }
-    total += (size_t)batch * f->plan.N * sc;                         // the states
+    total += (size_t)batch * P.N * sc;                                // the states
     bool open = false;                                                // a factor no closed tile holds
-    for (const auto &F : f->plan.factors)
-        if (F.xmask_union &&
-            !geometry(F.xlb, F.xhb, f->plan.n, tile_rows_max(f->dtype, 1, f->plan.N)).ok) open = true;
-    if (open) total += (size_t)std::min(batch, HS_MAX_BATCH) * f->plan.N * sc;   // its scratch state
+    for (const auto &F : P.factors)
+        if (F.xmask_union && !geometry(F.xlb, F.xhb, P.n, tile_rows_max(dtype, 1, P.N)).ok) open = true;
+    if (open) total += (size_t)std::min(batch, HS_MAX_BATCH) * P.N * sc;   // its scratch state
     // per-tile norm partials when renormalising (tiles of at least 64 rows)
-    total += (size_t)std::min(batch, HS_MAX_BATCH) * (size_t)(f->plan.N / 64 + 1) * 4 * sizeof(double);
+    total += (size_t)std::min(batch, HS_MAX_BATCH) * (size_t)(P.N / 64 + 1) * 4 * sizeof(double);
     total += sizeof(double) * ((size_t)HS_MAX_BATCH * hs::kReduceBlocks * 4 + HS_MAX_BATCH * 4);
     total += 64 * 1024;                                               // descriptors, flag
-    *bytes = total;
+    return total;
+}
+
+hs_status hs_footprint(hs_factors f, int batch, size_t *bytes) {
+    if (hs_status s = check_handle(f)) return s;
+    if (batch < 1 || !bytes) return fail(HS_EINVAL, "batch >= 1 and an output are required");
+    *bytes = footprint_bytes(f->plan, f->dtype, batch);
+    return HS_OK;
+}
+
+hs_status hs_footprint_dtype(hs_factors f, int batch, hs_dtype dtype, size_t *bytes) {
+    if (hs_status s = check_handle(f)) return s;
+    if (batch < 1 || !bytes) return fail(HS_EINVAL, "batch >= 1 and an output are required");
+    if (dtype != HS_C64 && dtype != HS_C128) return fail(HS_EINVAL, "dtype must be HS_C64 or HS_C128");
+    *bytes = footprint_bytes(f->plan, dtype, batch);
     return HS_OK;
 }
 
@@ -706,6 +776,14 @@ hs_status hs_dia_spmv(int n_diags, const long long *offsets, const void *const *
         if (j && offsets[j] <= offsets[j - 1]) return fail(HS_EINVAL, "offsets must ascend strictly");
         if (!diags[j]) return fail(HS_EINVAL, "null diagonal pointer");
         if (reinterpret_cast<uintptr_t>(diags[j]) % 16) return fail(HS_EINVAL, "diagonals must be 16-byte aligned");
+        std::string msg;
+        const size_t len = (size_t)(N - (offsets[j] < 0 ? -offsets[j] : offsets[j]));
+        if (!hs::device_range_ok(diags[j], len * sc, "diagonal", msg)) return fail(HS_EINVAL, msg);
+    }
+    {
+        std::string msg;
+        if (!hs::device_range_ok(x, span, "x", msg) || !hs::device_range_ok(y, span, "y", msg))
+            return fail(HS_EINVAL, msg);
     }
     std::vector<DiagDesc> hd;
     for (int c0 = 0; c0 < batch; c0 += HS_MAX_BATCH) {
@@ -750,6 +828,10 @@ static hs_status reduce_call(const void *A, int ta, const void *B, int tb, int b
 hs_status hs_norm2(const void *psi, int batch, long long N, hs_dtype dtype, void *stream, double *out) {
     if (!psi || !out || batch < 1 || N < 1) return fail(HS_EINVAL, "bad arguments");
     if (dtype != HS_C64 && dtype != HS_C128) return fail(HS_EINVAL, "bad dtype");
+    {
+        std::string msg;
+        if (!hs::device_range_ok(psi, (size_t)batch * N * elem_bytes(dtype), "state", msg)) return fail(HS_EINVAL, msg);
+    }
     std::vector<double> rec;
     if (hs_status s = reduce_call(psi, dtype, psi, dtype, batch, N, stream, false, rec)) return s;
     for (int b = 0; b < batch; ++b) out[b] = rec[4 * b + 2];
@@ -761,6 +843,12 @@ hs_status hs_fidelity(const void *phi, int phi_dtype, const void *psi, int psi_d
     if (!phi || !psi || !out || batch < 1 || N < 1) return fail(HS_EINVAL, "bad arguments");
     for (int t : {phi_dtype, psi_dtype})
         if (t != HS_C64 && t != HS_C128) return fail(HS_EINVAL, "bad dtype");
+    {
+        std::string msg;
+        if (!hs::device_range_ok(phi, (size_t)batch * N * elem_bytes(phi_dtype), "phi", msg) ||
+            !hs::device_range_ok(psi, (size_t)batch * N * elem_bytes(psi_dtype), "psi", msg))
+            return fail(HS_EINVAL, msg);
+    }
     std::vector<double> rec;
     if (hs_status s = reduce_call(phi, phi_dtype, psi, psi_dtype, batch, N, stream, true, rec)) return s;
     for (int b = 0; b < batch; ++b) {

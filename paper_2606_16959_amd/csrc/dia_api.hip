@@ -679,6 +679,10 @@ hs_status hs_dia_to_c64(hs_dia A, void *stream, hs_dia *out) {
 hs_status hs_dia_evolve(hs_dia U, void *psi, int batch, int steps, void *stream) {
     if (!U || !psi || batch < 1 || steps < 0) return dfail(HS_EINVAL, "bad arguments");
     if (reinterpret_cast<uintptr_t>(psi) % 16) return dfail(HS_EINVAL, "state pointer must be 16-byte aligned");
+    {
+        std::string msg;
+        if (!hs::device_range_ok(psi, (size_t)batch * U->N * U->elem(), "state", msg)) return dfail(HS_EINVAL, msg);
+    }
     if (steps == 0) return HS_OK;
     hipStream_t st = S(stream);
     const int64_t N = U->N;
@@ -766,6 +770,10 @@ hs_status hs_taylor_evolve(hs_dia H, void *psi, int batch, double dt, int K, int
     if (!H || !psi || batch < 1 || steps < 0 || K < 1 || K > 64 || !std::isfinite(dt))
         return dfail(HS_EINVAL, "bad arguments");
     if (reinterpret_cast<uintptr_t>(psi) % 16) return dfail(HS_EINVAL, "state pointer must be 16-byte aligned");
+    {
+        std::string msg;
+        if (!hs::device_range_ok(psi, (size_t)batch * H->N * H->elem(), "state", msg)) return dfail(HS_EINVAL, msg);
+    }
     if (steps == 0) return HS_OK;
     hipStream_t st = S(stream);
     const int64_t N = H->N;

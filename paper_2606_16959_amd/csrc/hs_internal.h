@@ -86,6 +86,7 @@ struct TileArgs {
     double *norm_out;        // or null: per tile and state, the FP64 sum of |y|^2 over the
                              // tile's rows at [(b * gridDim.x + tile) * 4 + 2] (others 0)
     int32_t stream_out;      // write y with non-temporal stores (see kStreamOutBytes)
+    int32_t pairs;           // closed complex64 launch whose every diagonal pairs (the pair kernel)
 };
 
 // States of at least this many bytes (the chunk of up to HS_MAX_BATCH states
@@ -118,8 +119,9 @@ int launch_construct(const ConstructArgs &a, int nd, int64_t max_len, bool c128,
 int launch_tile(const TileArgs &a, int batch, bool c128, bool closed, void *stream);
 // open launch with the Horner epilogue y = x0 + alpha (A x); y may alias x0, not x
 int launch_tile_horner(const TileArgs &a, int batch, bool c128, void *stream);
-int launch_diag_elementwise(void *y, const void *x, const void *diag, int64_t N, int batch,
-                            const double *nrm2, bool c128, void *stream);
+// the single-diagonal factor applied `steps` times in one pass (N even)
+int launch_diag_steps(void *y, const void *x, const void *diag, int64_t N, int batch, int steps,
+                      const double *nrm2, bool c128, bool stream_out, void *stream);
 int launch_reduce(const void *A, int ta, const void *B, int tb, int batch, int64_t N,
                   double *partial, int G, double *out, bool dot, void *stream);
 int launch_scale(void *psi, int64_t N, int batch, const double *nrm2, bool c128, void *stream);
@@ -167,6 +169,11 @@ int launch_dia_maxabs(const double *const *ptrs, const int64_t *offs, int64_t N,
 int launch_dia_fill(double *out, int64_t len, double re, double im, void *stream);
 int launch_diag_exp(const double *h, double *out, int64_t len, double dt, void *stream);
 void set_last_error(const std::string &m);   // message returned by hs_last_error()
+// Whether [p, p + bytes) is device (or managed) memory of the current device
+// and lies inside one allocation; otherwise false with a message naming `what`.
+// A host address handed to a kernel would fault the GPU, so every entry point
+// that takes caller memory checks it before enqueuing work.
+bool device_range_ok(const void *p, size_t bytes, const char *what, std::string &msg);
 hs_status parse_terms(int n, int n_terms, const char *const *strings, const double *coeffs,
                       std::vector<Term> &terms, std::string &msg);
 int launch_dia_to_c64(const double *const *src, float *const *dst, const int64_t *offs, int64_t N,

@@ -672,22 +672,276 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
     if (CLOSED && viol) atomicOr(a.viol, 1);
 }
 
-// Single main-diagonal factor: y[i] = v[i] x[i] (in place allowed).
-template <typename R, int B>
-__global__ __launch_bounds__(256) void diag_elementwise_kernel(C2<R> *y, const C2<R> *x,
-                                                               const C2<R> *__restrict__ v,
-                                                               int64_t N, const double *nrm2) {
+// ------------------------------------------------------------ pair kernel
+//
+// Closed complex64 launches in which every diagonal "pairs": the partners of
+// a thread's two rows are adjacent LDS entries starting on an even one.  That
+// holds for every diagonal of a strided tile (offsets are multiples of 2^qb
+// and W is even, so both rows of a pair sit on one level) and for a
+// contiguous tile whose offsets are all even.  Then both rows are in or out
+// of the tile together, the two coefficients of a pair are one 16-byte load,
+// and the two partners of every state one 16-byte LDS load (lanes read
+// consecutive 16-byte words: no bank conflicts).  The LDS stride between
+// states is a compile-time constant (the instantiation's row capacity), so
+// per-state LDS offsets are immediates.  The loop body has no branch between
+// diagonals of different shapes, so the coefficient loads of the next PF
+// diagonals stay in flight while this one is used.
+//
+// A coefficient whose partner lies outside the tile is zero for factors built
+// here (closure); such a row reads its own LDS entry and a nonzero value only
+// raises the violation flag.  Each row adds the same products in the same
+// order as the row-by-row kernel, with the same operands wherever the
+// coefficient is nonzero, so the two kernels give the same values.
+template <int B, int RPT, int NT>
+constexpr int pair_lds_rows() {
+    int rows = NT * RPT;
+    while (rows > 2 && (long)rows * B * 8 > HS_TILE_LDS_BYTES) rows >>= 1;
+    return rows;
+}
+
+#ifndef HS_PAIR_PF_BASE
+#define HS_PAIR_PF_BASE 30     // registers of the pair kernel besides per-pair indexing, accumulators, LDS operands and the load ring
+#endif
+// Diagonals whose coefficients a thread of the pair kernel keeps in flight:
+// about HS_TILE_INFLIGHT pair loads, cut while an estimate of its registers
+// (a fixed part, the accumulators and LDS operands, the ring of P * PF pairs)
+// would pass what NT
+// threads per workgroup leave each thread.
+template <int B, int P, int NT>
+constexpr int pair_pf() {
+    const int budget = NT >= 1024 ? 128 : 256;
+    int pf = HS_TILE_INFLIGHT / P >= 1 ? HS_TILE_INFLIGHT / P : 1;
+    while (pf > 1 && HS_PAIR_PF_BASE + 14 * P + 8 * P * B + 4 * P * pf > budget) --pf;
+    return pf;
+}
+
+template <int B, int RPT, int NT, bool STREAM>
+__global__ __launch_bounds__(NT) void dia_pair_kernel(TileArgs a) {
+    using R = float;
+    static_assert(RPT % 2 == 0, "rows come in pairs");
+    constexpr int P = RPT / 2;
+    constexpr int TS = pair_lds_rows<B, RPT, NT>();       // LDS rows per state (>= T)
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<R> *lds = reinterpret_cast<C2<R> *>(smem_raw);
+    const int T = a.T;
+    const int tid = threadIdx.x;
+    const int qb = a.qb, kb = a.kb, logW = a.logW;
+    const int W = 1 << logW;
+    const int L = 1 << kb;
+    int blk = blockIdx.x;
+    if (a.swizzle && (gridDim.x & 7) == 0) blk = (blk & 7) * (gridDim.x >> 3) + (blk >> 3);
+    const int hi = blk >> a.nlw_log;
+    const int lw = blk & ((1 << a.nlw_log) - 1);
+    const int base = (hi << (qb + kb)) | (lw << logW);
+    const C2<R> *x = reinterpret_cast<const C2<R> *>(a.x);  // may alias y (in place)
+    C2<R> *y = reinterpret_cast<C2<R> *>(a.y);
+    R scale[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) scale[b] = inv_norm<R>(a.nrm2, b);
+    auto row_of = [&](int i) { return base + ((i >> logW) << qb) + (i & (W - 1)); };
+
+    {
+        C2<R> u[P][2][B];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+            const int r0 = i0 < T ? row_of(i0) : base;
+#pragma unroll
+            for (int b = 0; b < B; ++b) ld2(x + b * a.stride, r0, u[p][0][b], u[p][1][b]);
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+            if (i0 < T)
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    lds[b * TS + i0] = cscale(u[p][0][b], scale[b]);
+                    lds[b * TS + i0 + 1] = cscale(u[p][1][b], scale[b]);
+                }
+        }
+    }
+
+    // Coefficients of PF diagonals are in flight: about HS_TILE_INFLIGHT
+    // 16-byte pair loads per thread, so that a workgroup of few row pairs per
+    // thread (large batches: one workgroup per CU) still keeps the CU's share
+    // of HBM busy while it computes.
+    constexpr int PF = pair_pf<B, P, NT>();
+    const int total = a.dstart[a.nf];
+    C2<R> acc[P][2][B];
+    bool viol = false;
+    auto clear_acc = [&]() {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int b = 0; b < B; ++b) acc[p][k][b] = C2<R>{(R)0, (R)0};
+    };
+    // coefficient pair of every row pair (even offsets: a pair is in or out
+    // of the diagonal's range as a whole; out-of-range pairs read entry 0 and
+    // are zeroed when used).  Diagonal j >= total is a placeholder of no
+    // entries: every lane reads entry 0 of the last diagonal (one cached
+    // line) and the values are never used; it keeps the number of loads per
+    // loop iteration fixed, so their waits stay exact.
+    auto load = [&](C2<R> (&c)[P][2], int j) {
+        const DiagDesc &dd = a.desc[j < total ? j : total - 1];
+        const C2<R> *cp = reinterpret_cast<const C2<R> *>(dd.ptr);
+        const int neg = dd.off < 0 ? dd.off : 0;
+        const int len = j < total ? dd.hi - dd.lo : 0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+            int e = row_of(i0) + neg;
+            e = (e >= 0 && e < len && i0 < T) ? e : 0;
+            ld2(cp, e, c[p][0], c[p][1]);
+        }
+    };
+    auto apply = [&](const C2<R> (&cc)[P][2], const DiagDesc &dd) {
+        const int mW = dd.m * W;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+            const int r0 = row_of(i0);
+            const bool valid = i0 < T && r0 >= dd.lo && r0 < dd.hi;
+            const C2<R> c0 = cmask(cc[p][0], valid), c1 = cmask(cc[p][1], valid);
+            const bool in = (unsigned)((i0 >> logW) + dd.m) < (unsigned)L;
+            const int sl = in ? i0 + mW : (i0 < T ? i0 : 0);
+            const bool nz = c0.re != (R)0 || c0.im != (R)0 || c1.re != (R)0 || c1.im != (R)0;
+            viol = viol || (!in && nz);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const f4v v = *reinterpret_cast<const f4v *>(&lds[b * TS + sl]);
+                cfma(acc[p][0][b], c0, C2<R>{v.x, v.y});
+                cfma(acc[p][1][b], c1, C2<R>{v.z, v.w});
+            }
+        }
+    };
+    int f = 0, fend = a.dstart[1];
+    // before the first diagonal of the next factor: the finished factor's
+    // output becomes the tile
+    auto next_factor = [&](int dj) {
+        if (dj == fend) {             // uniform over the workgroup
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int i0 = 2 * tid + 2 * NT * p;
+                if (i0 < T)
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        lds[b * TS + i0] = acc[p][0][b];
+                        lds[b * TS + i0 + 1] = acc[p][1][b];
+                    }
+            }
+            __syncthreads();
+            clear_acc();
+            ++f;
+            fend = a.dstart[f + 1];
+        }
+    };
+
+    C2<R> c[PF][P][2];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) load(c[u], u);
+    __syncthreads();
+    clear_acc();
+    int d0 = 0;
+    for (; d0 + PF <= total; d0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            next_factor(d0 + u);
+            apply(c[u], a.desc[d0 + u]);
+            load(c[u], d0 + u + PF);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        if (d0 + u < total) {
+            next_factor(d0 + u);
+            apply(c[u], a.desc[d0 + u]);
+        }
+    }
+
+    if (a.norm_out) {
+        double ss[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) ss[b] = 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+            if (i0 < T) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        const double re = (double)acc[p][k][b].re, im = (double)acc[p][k][b].im;
+                        ss[b] += re * re + im * im;
+                    }
+            }
+        }
+        __syncthreads();
+        double *red = reinterpret_cast<double *>(smem_raw);
+        const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const double v = wave_sum(ss[b]);
+            if (lane == 0) red[wave * B + b] = v;
+        }
+        __syncthreads();
+        if (tid < B) {
+            double tsum = 0.0;
+            for (int w = 0; w < NT / 64; ++w) tsum += red[w * B + tid];
+            double *o = a.norm_out + ((size_t)tid * gridDim.x + blockIdx.x) * 4;
+            o[0] = 0.0;
+            o[1] = 0.0;
+            o[2] = tsum;
+            o[3] = 0.0;
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int i0 = 2 * tid + 2 * NT * p;
+        if (i0 < T) {
+            const int r0 = row_of(i0);
+#pragma unroll
+            for (int b = 0; b < B; ++b) st2<STREAM>(y + b * a.stride, r0, acc[p][0][b], acc[p][1][b]);
+        }
+    }
+    if (viol) atomicOr(a.viol, 1);
+}
+
+// Single main-diagonal factor applied `steps` times: y[i] = v[i]^steps x[i]
+// for N even, each thread two adjacent entries (one 16-byte load of the
+// coefficients and of each state for complex64), the powers taken as
+// `steps` successive complex multiplications in registers in the order of
+// one step at a time, so the result equals `steps` single-step passes bit
+// for bit while the diagonal and the states cross HBM once.  In place
+// allowed.  STREAM: non-temporal output stores.
+template <typename R, int B, bool STREAM>
+__global__ __launch_bounds__(256) void diag_steps_kernel(C2<R> *y, const C2<R> *x, const C2<R> *__restrict__ v,
+                                                         int64_t N, int steps, const double *nrm2) {
     R scale[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) scale[b] = inv_norm<R>(nrm2, b);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const C2<R> c = v[i];
+    const int64_t npairs = N >> 1;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < npairs;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(2 * q);
+        C2<R> c0, c1;
+        ld2(v, i, c0, c1);
+        C2<R> u[B][2];
+#pragma unroll
+        for (int b = 0; b < B; ++b) ld2(x + b * N, i, u[b][0], u[b][1]);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            C2<R> acc{(R)0, (R)0};
-            cfma(acc, c, cscale(x[b * N + i], scale[b]));
-            y[b * N + i] = acc;
+            C2<R> a0 = cscale(u[b][0], scale[b]), a1 = cscale(u[b][1], scale[b]);
+            for (int s = 0; s < steps; ++s) {
+                C2<R> t0{(R)0, (R)0}, t1{(R)0, (R)0};
+                cfma(t0, c0, a0);
+                cfma(t1, c1, a1);
+                a0 = t0;
+                a1 = t1;
+            }
+            st2<STREAM>(y + b * N, i, a0, a1);
         }
     }
 }
@@ -824,6 +1078,35 @@ static int tile_launch(const TileArgs &a, int rows_per_thread, size_t lds, int g
     return (int)hipGetLastError();
 }
 
+// The pair kernel with the smallest rows-per-thread instantiation that
+// gives every tile row a thread (as tile_launch).
+template <int B, int RPT, int NT, bool STREAM>
+static int pair_launch(const TileArgs &a, int rows_per_thread, int grid, void *stream) {
+    if constexpr (RPT > 2) {
+        if (rows_per_thread <= RPT / 2) return pair_launch<B, RPT / 2, NT, STREAM>(a, rows_per_thread, grid, stream);
+    }
+    constexpr int TS = pair_lds_rows<B, RPT, NT>();
+    if (a.T > TS) return (int)hipErrorInvalidValue;
+    auto kern = dia_pair_kernel<B, RPT, NT, STREAM>;
+    const size_t lds = (size_t)TS * B * sizeof(C2<float>);
+    if (lds > 65536) {
+        static std::atomic<int> allowed{65536};
+        int cur = allowed.load();
+        while ((int)lds > cur) {
+            std::lock_guard<std::mutex> lock(lds_attr_mutex());
+            cur = allowed.load();
+            if ((int)lds <= cur) break;
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return (int)e;
+            allowed.store((int)lds);
+            cur = (int)lds;
+        }
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, S(stream), a);
+    return (int)hipGetLastError();
+}
+
 template <typename R, int B>
 static int tile_dispatch_b(const TileArgs &a, int mode, void *stream) {
     constexpr bool c128 = sizeof(R) == 8;
@@ -846,6 +1129,11 @@ static int tile_dispatch_b(const TileArgs &a, int mode, void *stream) {
     const int grid = (int)((a.N + a.T - 1) / a.T);
     const int need = (a.T + nt - 1) / nt;
     const bool st = a.stream_out != 0;         // ragged launches keep plain stores
+    if constexpr (sizeof(R) == 4) {
+        if (mode == kClosed && a.pairs)
+            return st ? pair_launch<B, RPT, NTC, true>(a, need, grid, stream)
+                      : pair_launch<B, RPT, NTC, false>(a, need, grid, stream);
+    }
     if (mode == kClosed)
         return st ? tile_launch<R, B, RPT, true, false, NTC, false, true>(a, need, lds, grid, stream)
                   : tile_launch<R, B, RPT, true, false, NTC>(a, need, lds, grid, stream);
@@ -884,28 +1172,32 @@ int launch_tile_horner(const TileArgs &a, int batch, bool c128, void *stream) {
                 : tile_dispatch<float>(a, batch, kHorner, stream);
 }
 
-template <typename R>
-static int diag_dispatch(void *y, const void *x, const void *v, int64_t N, int batch,
-                         const double *nrm2, void *stream) {
+template <typename R, bool STREAM>
+static int diag_steps_dispatch(void *y, const void *x, const void *v, int64_t N, int batch, int steps,
+                               const double *nrm2, void *stream) {
     C2<R> *py = reinterpret_cast<C2<R> *>(y);
     const C2<R> *px = reinterpret_cast<const C2<R> *>(x);
     const C2<R> *pv = reinterpret_cast<const C2<R> *>(v);
-    const dim3 g(grid_for(N, 256, 1 << 16)), blk(256);
+    const dim3 g(grid_for(N >> 1, 256, 1 << 20)), blk(256);
     switch (batch) {
-#define HS_DIAG_CASE(BB) \
-    case BB: hipLaunchKernelGGL((diag_elementwise_kernel<R, BB>), g, blk, 0, S(stream), py, px, pv, N, nrm2); break;
-        HS_DIAG_CASE(1) HS_DIAG_CASE(2) HS_DIAG_CASE(3) HS_DIAG_CASE(4)
-        HS_DIAG_CASE(5) HS_DIAG_CASE(6) HS_DIAG_CASE(7) HS_DIAG_CASE(8)
-#undef HS_DIAG_CASE
+#define HS_DSTEP_CASE(BB) \
+    case BB: hipLaunchKernelGGL((diag_steps_kernel<R, BB, STREAM>), g, blk, 0, S(stream), py, px, pv, N, steps, nrm2); break;
+        HS_DSTEP_CASE(1) HS_DSTEP_CASE(2) HS_DSTEP_CASE(3) HS_DSTEP_CASE(4)
+        HS_DSTEP_CASE(5) HS_DSTEP_CASE(6) HS_DSTEP_CASE(7) HS_DSTEP_CASE(8)
+#undef HS_DSTEP_CASE
         default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
 }
 
-int launch_diag_elementwise(void *y, const void *x, const void *diag, int64_t N, int batch,
-                            const double *nrm2, bool c128, void *stream) {
-    return c128 ? diag_dispatch<double>(y, x, diag, N, batch, nrm2, stream)
-                : diag_dispatch<float>(y, x, diag, N, batch, nrm2, stream);
+int launch_diag_steps(void *y, const void *x, const void *diag, int64_t N, int batch, int steps,
+                      const double *nrm2, bool c128, bool stream_out, void *stream) {
+    if (N < 2 || (N & 1) || steps < 1) return (int)hipErrorInvalidValue;
+    if (c128)
+        return stream_out ? diag_steps_dispatch<double, true>(y, x, diag, N, batch, steps, nrm2, stream)
+                          : diag_steps_dispatch<double, false>(y, x, diag, N, batch, steps, nrm2, stream);
+    return stream_out ? diag_steps_dispatch<float, true>(y, x, diag, N, batch, steps, nrm2, stream)
+                      : diag_steps_dispatch<float, false>(y, x, diag, N, batch, steps, nrm2, stream);
 }
 
 int launch_scale(void *psi, int64_t N, int batch, const double *nrm2, bool c128, void *stream) {

@@ -53,7 +53,9 @@ inline int tile_rows_max(int dtype, int batch, long long N, bool open = false) {
 // Launch-plan tuning knobs, read from the environment at every evolve (a
 // handle keeps one plan per batch size and knob setting): HAMSIM_WMIN_BYTES (shortest run of consecutive rows a
 // strided tile may have, default 256), HAMSIM_MAX_FUSE (factors per launch,
-// default 8), HAMSIM_XCD_SWIZZLE (which launches deal each XCD one contiguous
+// default 8), HAMSIM_PAIR_LDS (1: closed complex64 launches whose every
+// diagonal pairs run the pair kernel; 0: always the row-by-row kernel; same
+// results), HAMSIM_XCD_SWIZZLE (which launches deal each XCD one contiguous
 // eighth of the tiles instead of every eighth tile: 0 none, 1 all, 2 strided
 // tiles only, 3 contiguous tiles only; default 3: strided launches of
 // complex64 states measured 1-4% faster without it, contiguous ones faster
@@ -67,16 +69,16 @@ inline int env_int(const char *name, int dflt, int lo, int hi) {
     return (int)std::min<long>(hi, std::max<long>(lo, x));
 }
 struct PlanKey {
-    int chunk, fuse, wmin_bytes, max_fuse, swizzle;
+    int chunk, fuse, wmin_bytes, max_fuse, swizzle, pairs;
     bool operator<(const PlanKey &o) const {
-        return std::tie(chunk, fuse, wmin_bytes, max_fuse, swizzle) <
-               std::tie(o.chunk, o.fuse, o.wmin_bytes, o.max_fuse, o.swizzle);
+        return std::tie(chunk, fuse, wmin_bytes, max_fuse, swizzle, pairs) <
+               std::tie(o.chunk, o.fuse, o.wmin_bytes, o.max_fuse, o.swizzle, o.pairs);
     }
 };
 inline PlanKey plan_key(int chunk, bool fuse) {
     return PlanKey{chunk, fuse ? 1 : 0, env_int("HAMSIM_WMIN_BYTES", 256, 8, 1 << 20),
                    env_int("HAMSIM_MAX_FUSE", kMaxRun, 1, kMaxRun),
-                   env_int("HAMSIM_XCD_SWIZZLE", 3, 0, 3)};
+                   env_int("HAMSIM_XCD_SWIZZLE", 3, 0, 3), env_int("HAMSIM_PAIR_LDS", 1, 0, 1)};
 }
 // Whether a launch of geometry `g` deals contiguous eighths of its tiles to the XCDs.
 inline bool swizzled(int mode, const Geo &g) {
@@ -183,6 +185,7 @@ inline TileArgs open_args(const Geo &geo, const DiagDesc *ddev, int nd, const vo
     a.swizzle = 0;
     a.ragged = (N % geo.T) != 0;
     a.stream_out = 0;
+    a.pairs = 0;
     return a;
 }
 

@@ -195,6 +195,75 @@ def test_evolve_maxcut_n24_full_size_batched():
     f.close()
 
 
+def _c64_run_bound(n_factor_apps, max_diags):
+    """2-norm bound of the complex64 error of a whole evolution: each factor
+    application rounds every stored coefficient to FP32 and accumulates at
+    most `max_diags` products in FP32 (relative error <= max_diags * 2^-24
+    per application, counting the coefficient rounding), and a unitary step
+    does not amplify earlier errors, so the errors add over the run."""
+    return n_factor_apps * max_diags * 2.0 ** -24
+
+
+def test_evolve_tfim_5x5_n26_full_length_against_oracle():
+    """The whole stated run of the n = 26 2-D TFIM (50 steps, 9 factors of at
+    most 15 diagonals) against the FP64 oracle of the same product (Eq. 4,
+    fidelity as in Section 4.3): complex64 at fidelity >= 1 - 1e-6 and within
+    the accumulated FP32 bound, complex128 within 1e-12; the two GPU paths
+    also agree with each other."""
+    hs, torch = hs_gpu()
+    H = workload_hamiltonian("tfim_5x5_ancilla_n26")
+    psi0 = ws.random_phase_state(26, 3, np.complex128)
+    note("full-length oracle run tfim_5x5_ancilla_n26, 50 steps (host)")
+    ref = oracle_run(H, 16, 1.0, 50, psi0, threads=oracle_threads())
+    got = {}
+    for dtype, npd in (("c64", np.complex64), ("c128", np.complex128)):
+        note(f"evolve tfim_5x5_ancilla_n26 {dtype}, all 50 steps")
+        f = hs.build_factors(H.strings, H.coeffs, 26, 1.0, 50, 16, dtype=dtype)
+        nf, maxd = f.n_factors, max(len(x["offsets"]) for x in f.describe()["factors"])
+        p = _to_dev(torch, psi0, npd)
+        hs.evolve(f, p, 50)
+        got[dtype] = p.cpu().numpy().astype(np.complex128)
+        f.close()
+        del p
+        torch.cuda.empty_cache()
+    g64, g128 = got["c64"], got["c128"]
+    bound = _c64_run_bound(50 * nf, maxd)
+    assert np.min(fid(g64, ref)) >= 1 - 1e-6
+    assert np.linalg.norm(g64 - ref) <= bound
+    assert abs(np.linalg.norm(g64) - 1.0) <= bound
+    assert np.abs(g128 - ref).max() <= 1e-12 and np.min(fid(g128, ref)) >= 1 - 1e-12
+    assert np.min(fid(g64, g128)) >= 1 - 1e-6
+
+
+def test_evolve_maxcut_n24_full_length_batched_against_oracle():
+    """All 200 steps of the n = 24 MaxCut run with 8 states batched (DIA SpMM),
+    states 0, 1 and 7 against the FP64 oracle; state 7 also equals its
+    single-state run bit for bit after the whole run."""
+    hs, torch = hs_gpu()
+    H = workload_hamiltonian("maxcut_3reg_n24")
+    psi0 = ws.workload_states("maxcut_3reg_n24", np.complex64)
+    note("evolve maxcut_3reg_n24 B=8 c64, all 200 steps")
+    f = hs.build_factors(H.strings, H.coeffs, 24, 1.0, 200, 16, dtype="c64")
+    nf, maxd = f.n_factors, max(len(x["offsets"]) for x in f.describe()["factors"])
+    p = _to_dev(torch, psi0, np.complex64)
+    hs.evolve(f, p, 200)
+    got = p.cpu().numpy()
+    one = _to_dev(torch, psi0[7:8], np.complex64)
+    hs.evolve(f, one, 200)
+    assert np.array_equal(one.cpu().numpy()[0], got[7])
+    f.close()
+    del p, one
+    note("full-length oracle run maxcut_3reg_n24, states 0, 1, 7, 200 steps (host)")
+    cols = [0, 1, 7]
+    ref = oracle_run(H, 16, 1.0, 200, psi0[cols].astype(np.complex128), threads=oracle_threads())
+    g = got[cols].astype(np.complex128)
+    bound = _c64_run_bound(200 * nf, maxd)
+    assert np.all(fid(g, ref) >= 1 - 1e-6)
+    for b in range(len(cols)):
+        assert np.linalg.norm(g[b] - ref[b]) <= bound
+        assert abs(np.linalg.norm(g[b]) - 1.0) <= bound
+
+
 def test_fused_unfused_split_and_repeat_are_bitwise_equal():
     hs, torch = hs_gpu()
     H = workload_hamiltonian("heisenberg_chain_n20")
@@ -238,6 +307,69 @@ def test_renorm_keeps_unit_norm_and_fidelity():
 
 
 # ------------------------------------------------------------------ (a3) single diagonal
+
+def _maxcut_cost(n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    edges = wh.random_regular_graph(n, 3, rng)
+    return wh.maxcut(n, edges, rng.uniform(1.0, 10.0, len(edges)), mixer=0.0)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_diagonal_steps_in_one_pass_equal_step_by_step(dtype):
+    """A diagonal Hamiltonian's step is one diagonal factor; without
+    renormalisation the library applies all steps in one pass.  That pass
+    equals one call per step bit for bit (batch of 3), and with
+    renormalisation (step by step) it stays within rounding of it."""
+    hs, torch = hs_gpu()
+    H = _maxcut_cost(16, 9)
+    npd = np.complex128 if dtype == "c128" else np.complex64
+    note(f"diagonal steps one pass vs step by step {dtype}")
+    f = hs.build_factors(H.strings, H.coeffs, 16, 1.0, 37, 16, dtype=dtype)
+    assert f.n_factors == 1 and f.describe()["factors"][0]["offsets"] == [0]
+    psi0 = np.stack([ws.random_phase_state(16, s, npd) for s in (1, 2, 3)])
+    a = _to_dev(torch, psi0, npd)
+    hs.evolve(f, a, 37)
+    b = _to_dev(torch, psi0, npd)
+    for _ in range(37):
+        hs.evolve(f, b, 1)
+    c = _to_dev(torch, psi0, npd)
+    hs.evolve(f, c, 11)
+    hs.evolve(f, c, 26)
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    assert np.array_equal(a.cpu().numpy(), c.cpu().numpy())
+    r = _to_dev(torch, psi0, npd)
+    hs.evolve(f, r, 37, renorm=True)
+    tol = 1e-12 if dtype == "c128" else 2e-5
+    got, ref = r.cpu().numpy().astype(np.complex128), a.cpu().numpy().astype(np.complex128)
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+    f.close()
+
+
+def test_diagonal_only_full_size_n26_matches_closed_form_on_sampled_rows():
+    """MaxCut cost (no mixer) at n = 26, complex64, 200 steps in one pass: the
+    diagonal factor exp(-i dt E) of Section 3.4 applied 200 times equals
+    exp(-i t E) psi0 (exact Trotterisation of a diagonal H) to FP32
+    rounding, on rows at both ends and spread over the state."""
+    hs, torch = hs_gpu()
+    n, t, r = 26, 1.0, 200
+    H = _maxcut_cost(n, 26)
+    terms = opauli.parse_terms(H.strings, H.coeffs, n)
+    part = ofac.first_fit(terms, 16, t)
+    fac = part.factor_list(merge_diag=True)[0]
+    rng = np.random.default_rng(26)
+    rows = np.unique(np.concatenate([np.arange(64), (1 << n) - 1 - np.arange(64),
+                                     rng.integers(0, 1 << n, 4096)]))
+    note("diagonal-only maxcut cost n=26 c64, 200 steps in one pass")
+    f = hs.build_factors(H.strings, H.coeffs, n, t, r, 16, dtype="c64")
+    psi0 = ws.random_phase_state(n, 5, np.complex64)
+    p = _to_dev(torch, psi0, np.complex64)
+    hs.evolve(f, p, r)
+    got = p.cpu().numpy()[rows].astype(np.complex128)
+    f.close()
+    exact = ofac.factor_entries(terms, part, fac, n, t, rows, 0) * psi0[rows].astype(np.complex128)
+    # r complex multiplications in FP32, each within a few ulp
+    assert np.abs(got - exact).max() <= r * 4 * 2.0 ** -24 * np.abs(exact).max()
+
 
 def test_diagonal_only_hamiltonian_matches_closed_form():
     hs, torch = hs_gpu()
@@ -580,17 +712,17 @@ def test_maximum_size_n30_sampled_rows(batch, renorm):
 
 @pytest.mark.parametrize("order,ratio,rs", [(1, 2.0, (16, 32, 64)), (2, 4.0, (8, 16, 32)), (4, 16.0, (4, 8, 16))])
 def test_error_scaling_on_the_gpu(order, ratio, rs):
-    """complex128 GPU evolutions against exp(-iHt) (dense eigendecomposition,
-    n = 7): the global error falls by 2^order per doubling of r."""
+    """complex128 GPU evolutions against exp(-iHt) from the dense
+    eigendecomposition (n = 7): the global error falls by 2^order per
+    doubling of r."""
     hs, torch = hs_gpu()
-    import scipy.linalg as sl
     n, t = 7, 1.0
     H = wh.tfim_1d(n, 1.0, 1.0)
     Hd = opauli.dense_hamiltonian(opauli.parse_terms(H.strings, H.coeffs, n), n)
     rng = np.random.default_rng(order)
     psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
     psi0 /= np.linalg.norm(psi0)
-    exact = sl.expm(-1j * t * Hd) @ psi0
+    exact = opauli.dense_propagator(Hd, t) @ psi0
     note(f"error scaling order {order} r={rs}")
     errs = []
     for r in rs:
