@@ -243,6 +243,24 @@ hs_status hs_norm2(const void *psi, int batch, long long N, hs_dtype dtype, void
 hs_status hs_fidelity(const void *phi, int phi_dtype, const void *psi, int psi_dtype,
                       int batch, long long N, void *stream, double *out);
 
+/*
+ * hs_fidelity_noalloc -- hs_fidelity for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  It allocates nothing (no hipMalloc, no library
+ * allocation) and does not synchronise: the same FP64 reduction kernels as
+ * hs_fidelity run on `stream` with their partial sums in a static device
+ * array of 256.25 KiB per GPU (held until the process ends), and
+ * out_dev (device, [batch][5] doubles, the layout of hs_fidelity's output)
+ * receives the same values, bit for bit, when the stream reaches it.
+ * batch is 1..HS_MAX_BATCH (8); larger batches return HS_EINVAL.  Every call
+ * on one GPU shares that array: calls that overlap in time on one GPU (on
+ * different streams or threads) race and must be ordered by the caller.
+ * Nothing needs clearing between calls (each call writes every partial it
+ * reads).
+ */
+hs_status hs_fidelity_noalloc(const void *phi, int phi_dtype, const void *psi, int psi_dtype,
+                              int batch, long long N, void *stream, double *out_dev);
+
 /* ------------------------------------------------------------------------
  * General operators in the diagonal layout, device resident.  These carry
  * the paper's single-propagator pipeline: H is stored by its diagonals, its

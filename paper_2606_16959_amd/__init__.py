@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import (HS_C64, HS_C128, HS_MERGE_DIAG, HS_NO_FUSE, HS_ORDER2, HS_ORDER4,  # noqa: F401
                    HS_RENORM, HamsimError)
 
-__all__ = ["Factors", "plan", "build_factors", "evolve", "norm2", "fidelity", "dia_spmv",
+__all__ = ["Factors", "plan", "build_factors", "evolve", "norm2", "fidelity", "fidelity_noalloc", "dia_spmv",
            "HamsimError", "dtype_code"]
 
 
@@ -239,6 +239,23 @@ def fidelity(phi, psi, stream=None) -> np.ndarray:
     _lib.check(_lib.load().hs_fidelity(ctypes.c_void_p(phi.data_ptr()), cp,
                                        ctypes.c_void_p(psi.data_ptr()), cq, batch, N,
                                        _stream_ptr(stream), out.ctypes.data))
+    return out
+
+
+def fidelity_noalloc(phi, psi, out, stream=None):
+    """fidelity() into a device float64 tensor out [B, 5], enqueued on the
+    stream without allocating or synchronising (B <= 8; see hs_fidelity_noalloc)."""
+    batch, N, cp = _state_args(phi)
+    b2, N2, cq = _state_args(psi)
+    if (batch, N) != (b2, N2):
+        raise ValueError("shape mismatch")
+    import torch
+    if (not out.is_cuda or out.dtype != torch.float64 or not out.is_contiguous()
+            or out.numel() != batch * 5 or out.device != phi.device):
+        raise ValueError("out must be a contiguous float64 device tensor of batch * 5 entries")
+    _lib.check(_lib.load().hs_fidelity_noalloc(ctypes.c_void_p(phi.data_ptr()), cp,
+                                               ctypes.c_void_p(psi.data_ptr()), cq, batch, N,
+                                               _stream_ptr(stream), ctypes.c_void_p(out.data_ptr())))
     return out
 
 

@@ -45,6 +45,7 @@ _SIG = {
     "hs_dia_spmv": (_I, [_I, _P, _P, _P, _P, _I, _LL, _I, _P]),
     "hs_norm2": (_I, [_P, _I, _LL, _I, _P, _P]),
     "hs_fidelity": (_I, [_P, _I, _P, _I, _I, _LL, _P, _P]),
+    "hs_fidelity_noalloc": (_I, [_P, _I, _P, _I, _I, _LL, _P, _P]),
     "hs_dia_from_pauli": (_I, [_I, _I, _P, _P, _P, ctypes.POINTER(_P)]),
     "hs_dia_from_host": (_I, [_LL, _I, _P, _P, _P, ctypes.POINTER(_P)]),
     "hs_dia_info": (_I, [_P, ctypes.POINTER(_LL), ctypes.POINTER(_I), ctypes.POINTER(_I)]),

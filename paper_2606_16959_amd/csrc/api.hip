@@ -863,3 +863,68 @@ hs_status hs_fidelity(const void *phi, int phi_dtype, const void *psi, int psi_d
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- no allocation
+//
+// Scratch of hs_fidelity_noalloc: the FP64 reduction partials of up to
+// HS_MAX_BATCH states ([8][kReduceBlocks][4]) and their records ([8][4]),
+// 256.25 KiB in every GPU the library runs on, held until the process ends.
+// Host code never uses the array's name as an address: each device's copy is
+// found once with hipGetSymbolAddress and its pointer kept per device.
+namespace {
+constexpr size_t kNoAllocPartials = (size_t)HS_MAX_BATCH * hs::kReduceBlocks * 4;
+constexpr size_t kNoAllocDoubles = kNoAllocPartials + (size_t)HS_MAX_BATCH * 4;
+constexpr int kNoAllocDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+static double *noalloc_scratch(std::string &msg) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        msg = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kNoAllocDevices) {
+        msg = "device index beyond the 64 devices the scratch table covers";
+        return nullptr;
+    }
+    static std::mutex mu;
+    static double *ptr[kNoAllocDevices] = {};
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            msg = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        ptr[dev] = static_cast<double *>(p);
+    }
+    return ptr[dev];
+}
+
+extern "C" hs_status hs_fidelity_noalloc(const void *phi, int phi_dtype, const void *psi, int psi_dtype, int batch,
+                                         long long N, void *stream, double *out_dev) {
+    if (!phi || !psi || !out_dev || N < 1) return fail(HS_EINVAL, "bad arguments");
+    if (batch < 1 || batch > HS_MAX_BATCH)
+        return fail(HS_EINVAL, "batch must be 1.." + std::to_string(HS_MAX_BATCH) +
+                                   ": the static scratch holds the partial sums of that many states");
+    for (int t : {phi_dtype, psi_dtype})
+        if (t != HS_C64 && t != HS_C128) return fail(HS_EINVAL, "bad dtype");
+    std::string msg;
+    if (!hs::device_range_ok(phi, (size_t)batch * N * elem_bytes(phi_dtype), "phi", msg) ||
+        !hs::device_range_ok(psi, (size_t)batch * N * elem_bytes(psi_dtype), "psi", msg) ||
+        !hs::device_range_ok(out_dev, (size_t)batch * 5 * sizeof(double), "out", msg))
+        return fail(HS_EINVAL, msg);
+    double *s = noalloc_scratch(msg);
+    if (!s) return fail(HS_EDEVICE, msg);
+    double *rec = s + kNoAllocPartials;
+    // every partial and record the kernels read is written by this call first
+    int e = hs::launch_reduce(phi, phi_dtype, psi, psi_dtype, batch, N, s, hs::kReduceBlocks, rec, true, stream);
+    if (e) return hip_fail((hipError_t)e, "reduction");
+    e = hs::launch_fidelity_records(rec, batch, out_dev, stream);
+    if (e) return hip_fail((hipError_t)e, "fidelity records");
+    return HS_OK;
+}

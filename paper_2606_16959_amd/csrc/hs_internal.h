@@ -127,6 +127,8 @@ int launch_reduce(const void *A, int ta, const void *B, int tb, int batch, int64
 int launch_scale(void *psi, int64_t N, int batch, const double *nrm2, bool c128, void *stream);
 // records [batch][4] from per-block partials [batch][G][4], in a fixed order
 int launch_reduce_partials(const double *partial, int G, int batch, double *out, void *stream);
+// [batch][5] fidelity records (Re, Im, <phi|phi>, <psi|psi>, F) from reduction records (batch <= 64)
+int launch_fidelity_records(const double *rec, int batch, double *out, void *stream);
 
 // general operators in the diagonal layout (dia_ops.hip)
 struct PauliDiaArgs {

@@ -1013,6 +1013,22 @@ __global__ __launch_bounds__(256) void reduce_final_kernel(const double *partial
     if (threadIdx.x < 4) out[b * 4 + threadIdx.x] = red[0][threadIdx.x];
 }
 
+// Fidelity records: out[b] = (Re, Im <phi|psi>, <phi|phi>, <psi|psi>, F) from
+// the reduction records, F = (Re^2 + Im^2) / (<phi|phi> <psi|psi>) evaluated
+// as separate roundings (no fused multiply-add), as the host evaluates it.
+__global__ void fidelity_records_kernel(const double *rec, int batch, double *out) {
+#pragma clang fp contract(off)
+    const int b = threadIdx.x;
+    if (b < batch) {
+        const double re = rec[4 * b], im = rec[4 * b + 1], np = rec[4 * b + 2], nq = rec[4 * b + 3];
+        out[5 * b + 0] = re;
+        out[5 * b + 1] = im;
+        out[5 * b + 2] = np;
+        out[5 * b + 3] = nq;
+        out[5 * b + 4] = (re * re + im * im) / (np * nq);
+    }
+}
+
 // ------------------------------------------------------------ launchers
 
 static inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -1232,6 +1248,11 @@ int launch_reduce(const void *A, int ta, const void *Bv, int tb, int batch, int6
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
     hipLaunchKernelGGL(reduce_final_kernel, dim3(batch), blk, 0, S(stream), partial, G, out);
+    return (int)hipGetLastError();
+}
+
+int launch_fidelity_records(const double *rec, int batch, double *out, void *stream) {
+    hipLaunchKernelGGL(fidelity_records_kernel, dim3(1), dim3(64), 0, S(stream), rec, batch, out);
     return (int)hipGetLastError();
 }
 
