@@ -275,6 +275,8 @@ SWEEP = [
     ("wmin2048", {"HAMSIM_WMIN_BYTES": "2048"}),
     ("fuse1", {"HAMSIM_MAX_FUSE": "1"}),
     ("fuse3", {"HAMSIM_MAX_FUSE": "3"}),
+    ("pair_kernel_all", {"HAMSIM_PAIR_LDS": "2"}),
+    ("pair_kernel_off", {"HAMSIM_PAIR_LDS": "0"}),
 ]
 
 

@@ -130,12 +130,15 @@ hs_status hs_build_factors(int n_qubits, int n_terms, const char *const *pauli_t
  * next step loads the state, and once more at the end), HS_NO_FUSE.
  * complex64 states accumulate in FP32 over ascending offsets; complex128 in
  * FP64.  Results do not depend on the batch size or on fusion.
- * Launch shapes follow three environment variables, read at every call (a
+ * Launch shapes follow four environment variables, read at every call (a
  * handle keeps one launch plan per setting): HAMSIM_WMIN_BYTES (shortest
  * row run of a strided tile, default 256), HAMSIM_MAX_FUSE (factors per
- * launch, 1..8, default 8) and HAMSIM_XCD_SWIZZLE (which launches deal
+ * launch, 1..8, default 8), HAMSIM_XCD_SWIZZLE (which launches deal
  * contiguous eighths of their tiles to the 8 XCDs: 0 none, 1 all, 2 strided,
- * 3 contiguous, default 3).  Results are the same bits for every setting.
+ * 3 contiguous, default 3) and HAMSIM_PAIR_LDS (which closed complex64
+ * launches whose row pairs read adjacent LDS partners use the pair kernel:
+ * 0 none, 1 all but one-state strided launches with row runs under 1 KiB,
+ * 2 all; default 1).  Results are the same bits for every setting.
  * A factor whose coupling range fits no tile held in LDS (e.g. X_0 X_{n-1}
  * at large n) is applied out of place into a scratch state (allocated on
  * first use, counted by hs_footprint) and copied back.  Calls that share a

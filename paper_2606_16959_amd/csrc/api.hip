@@ -231,6 +231,8 @@ hs_status make_evolve_plan(hs_factors_s *h, const PlanKey &key, EvolvePlan &ep, 
             run.desc_start = (int)ep.host_desc.size();
             run.dstart.push_back(0);
             run.pairs = key.pairs && h->dtype == HS_C64 && !run.open && !run.elementwise;
+            if (key.pairs == 1 && run.geo.qb > 0 && run.launch_batch == 1 && ((size_t)1 << run.geo.logW) * sc < 1024)
+                run.pairs = false;
             for (int k : run.factors) {
                 const Factor &Fk = P.factors[k];
                 for (size_t j = 0; j < Fk.offs.size(); ++j) {

@@ -53,9 +53,11 @@ inline int tile_rows_max(int dtype, int batch, long long N, bool open = false) {
 // Launch-plan tuning knobs, read from the environment at every evolve (a
 // handle keeps one plan per batch size and knob setting): HAMSIM_WMIN_BYTES (shortest run of consecutive rows a
 // strided tile may have, default 256), HAMSIM_MAX_FUSE (factors per launch,
-// default 8), HAMSIM_PAIR_LDS (1: closed complex64 launches whose every
-// diagonal pairs run the pair kernel; 0: always the row-by-row kernel; same
-// results), HAMSIM_XCD_SWIZZLE (which launches deal each XCD one contiguous
+// default 8), HAMSIM_PAIR_LDS (which closed complex64 launches whose every
+// diagonal pairs run the pair kernel: 2 all, 1 all but one-state strided
+// launches whose row runs are under 1 KiB -- translation-bound launches, where
+// the row-by-row kernel measured faster -- 0 none; same results; default 1),
+// HAMSIM_XCD_SWIZZLE (which launches deal each XCD one contiguous
 // eighth of the tiles instead of every eighth tile: 0 none, 1 all, 2 strided
 // tiles only, 3 contiguous tiles only; default 3: strided launches of
 // complex64 states measured 1-4% faster without it, contiguous ones faster
@@ -78,7 +80,7 @@ struct PlanKey {
 inline PlanKey plan_key(int chunk, bool fuse) {
     return PlanKey{chunk, fuse ? 1 : 0, env_int("HAMSIM_WMIN_BYTES", 256, 8, 1 << 20),
                    env_int("HAMSIM_MAX_FUSE", kMaxRun, 1, kMaxRun),
-                   env_int("HAMSIM_XCD_SWIZZLE", 3, 0, 3), env_int("HAMSIM_PAIR_LDS", 1, 0, 1)};
+                   env_int("HAMSIM_XCD_SWIZZLE", 3, 0, 3), env_int("HAMSIM_PAIR_LDS", 1, 0, 2)};
 }
 // Whether a launch of geometry `g` deals contiguous eighths of its tiles to the XCDs.
 inline bool swizzled(int mode, const Geo &g) {
