@@ -395,6 +395,16 @@ def other_workloads(torch, steps=10, warmup=2, pool=None):
         row = {"workload": cfg, "n": H.n, "batch": B, "dtype": dtype, "renorm": renorm,
                "launches_per_step": len(launches), "ms_per_step": round(ms, 4),
                "gb_per_step": round(sum(per) / 1e9, 3), "gbs": round(sum(per) / ms / 1e6, 1)}
+        if H.n <= 11 and not renorm:
+            # small states: the whole stated run is one call (one launch of the
+            # whole-evolution kernel), timed as a run
+            e0.record()
+            for _ in range(5):
+                hs.evolve(f, psi, run["steps"])
+            e1.record()
+            torch.cuda.synchronize()
+            row["ms_per_run"] = round(e0.elapsed_time(e1) / 5, 4)
+            row["run_steps"] = run["steps"]
         if B > 1:
             row["ms_per_state_step"] = round(ms / B, 4)
         if cfg in ACCURACY_STEPS:

@@ -145,6 +145,11 @@ hs_status hs_build_factors(int n_qubits, int n_terms, const char *const *pauli_t
  * handle share its workspace, so they must be ordered on one stream.
  * The state is checked (device memory, batch * N elements inside one
  * allocation) before anything else, also when steps is 0.
+ * Small states (N <= 2048 complex64 or 1024 complex128 rows by default; the
+ * environment variable HAMSIM_WHOLE_MAX_ROWS sets the cap, at most 8192 /
+ * 4096 rows, 0 = never) evolve without HS_RENORM or HS_NO_FUSE in one launch
+ * for all steps and states, each state held in LDS by one workgroup (same
+ * values as the launch per run and step).
  */
 hs_status hs_evolve(hs_factors f, void *psi, int batch, int steps, void *stream,
                     unsigned flags);

@@ -146,6 +146,11 @@ struct hs_factors_s {
     hipStream_t alloc_stream = nullptr;   // device memory is stream-ordered on this stream
     std::map<PlanKey, EvolvePlan> plans;
     std::mutex mu;
+    // whole-evolution tables (small states), built on first use
+    bool whole_ready = false;
+    std::vector<hs::WholeEntry> whole_walk;
+    int32_t whole_part_off[5] = {0, 0, 0, 0, 0};
+    hs::WholeEntry *whole_walk_dev = nullptr;
 
     double *partials() { return work_dev; }
     double *records() { return work_dev + (size_t)HS_MAX_BATCH * hs::kReduceBlocks * 4; }
@@ -161,6 +166,7 @@ struct hs_factors_s {
         if (scratch_dev) (void)hipFreeAsync(scratch_dev, alloc_stream);
         if (norm_dev) (void)hipFreeAsync(norm_dev, alloc_stream);
         if (work_dev) (void)hipFreeAsync(work_dev, alloc_stream);
+        if (whole_walk_dev) (void)hipFreeAsync(whole_walk_dev, alloc_stream);
     }
 };
 
@@ -315,6 +321,50 @@ hs_status launch_run(hs_factors_s *h, const EvolvePlan &ep, const Run &run, void
             HS_HIP(hipMemcpyAsync(p, h->scratch_dev, (size_t)nb * P.N * sc, hipMemcpyDeviceToDevice,
                                   reinterpret_cast<hipStream_t>(stream)), "copy back");
     }
+    return HS_OK;
+}
+
+// Rows up to which hs_evolve runs a whole evolution in one launch
+// (HAMSIM_WHOLE_MAX_ROWS, capped by the kernel's limit; 0 never).  The
+// default is where one workgroup per state stops beating the launch per run
+// and step on MI355X: 2048 complex64 rows (n <= 11: 1.3-3x faster, n = 12
+// and 13 up to 2.7x slower) and 1024 complex128 rows.
+int64_t whole_max_rows(int dtype) {
+    const int lim = dtype == HS_C128 ? hs::kWholeRowsC128 : hs::kWholeRowsC64;
+    const int dflt = dtype == HS_C128 ? 1024 : 2048;
+    return env_int("HAMSIM_WHOLE_MAX_ROWS", dflt, 0, lim);
+}
+
+// The whole-evolution kernel's walk: for each step part, one entry per
+// diagonal it applies, in order (factor by factor, ascending offsets).
+hs_status make_whole_tables(hs_factors_s *h, void *stream) {
+    const Plan &P = h->plan;
+    const size_t sc = elem_bytes(h->dtype);
+    h->whole_walk.clear();
+    for (int q = 0; q < kParts; ++q) {
+        h->whole_part_off[q] = (int32_t)h->whole_walk.size();
+        for (int fi : part_sequence(P, q)) {
+            const Factor &F = P.factors[fi];
+            for (size_t j = 0; j < F.offs.size(); ++j) {
+                const int64_t d = F.offs[j];
+                hs::WholeEntry e{};
+                e.ptr = static_cast<const char *>(F.dev) + F.elem_off[j] * sc;
+                e.off = (int32_t)d;
+                e.lo = (int32_t)std::max<int64_t>(0, -d);
+                e.hi = (int32_t)std::min<int64_t>(P.N, P.N - d);
+                e.last = j + 1 == F.offs.size() ? 1u : 0u;
+                h->whole_walk.push_back(e);
+            }
+        }
+    }
+    h->whole_part_off[kParts] = (int32_t)h->whole_walk.size();
+    if (h->whole_walk.empty()) return fail(HS_EINVAL, "no diagonals to apply");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const size_t nw = h->whole_walk.size() * sizeof(hs::WholeEntry);
+    HS_HIP(hipMallocAsync(reinterpret_cast<void **>(&h->whole_walk_dev), nw, st), "hipMallocAsync(whole walk)");
+    // the host vector lives as long as the handle, so an ordered async copy is safe
+    HS_HIP(hipMemcpyAsync(h->whole_walk_dev, h->whole_walk.data(), nw, hipMemcpyHostToDevice, st), "whole walk");
+    h->whole_ready = true;
     return HS_OK;
 }
 
@@ -494,11 +544,26 @@ hs_status hs_evolve(hs_factors f, void *psi, int batch, int steps, void *stream,
     }
     if (steps == 0) return HS_OK;
     std::lock_guard<std::mutex> lock(f->mu);
-    const bool fuse = !(flags & HS_NO_FUSE);
-    const bool renorm = (flags & HS_RENORM) != 0;
     int cur_dev = 0;
     HS_HIP(hipGetDevice(&cur_dev), "hipGetDevice");
     if (cur_dev != f->device) return fail(HS_EINVAL, "current device differs from the build device");
+    if (!(flags & (HS_RENORM | HS_NO_FUSE)) && P.N <= whole_max_rows(f->dtype)) {
+        // a small state: the whole evolution of every state in one launch
+        if (!f->whole_ready)
+            if (hs_status s = make_whole_tables(f, stream)) return s;
+        hs::WholeArgs w{};
+        w.psi = psi;
+        w.stride = P.N;
+        w.N = (int32_t)P.N;
+        w.steps = steps;
+        w.walk = f->whole_walk_dev;
+        for (int q = 0; q <= kParts; ++q) w.part_off[q] = f->whole_part_off[q];
+        int e = hs::launch_whole(w, batch, f->dtype == HS_C128, stream);
+        if (e) return hip_fail((hipError_t)e, "whole-evolution kernel launch");
+        return HS_OK;
+    }
+    const bool fuse = !(flags & HS_NO_FUSE);
+    const bool renorm = (flags & HS_RENORM) != 0;
     for (int c0 = 0; c0 < batch; c0 += HS_MAX_BATCH) {
         const int chunk = std::min(HS_MAX_BATCH, batch - c0);
         const PlanKey key = plan_key(chunk, fuse);

@@ -119,6 +119,28 @@ int launch_construct(const ConstructArgs &a, int nd, int64_t max_len, bool c128,
 int launch_tile(const TileArgs &a, int batch, bool c128, bool closed, void *stream);
 // open launch with the Horner epilogue y = x0 + alpha (A x); y may alias x0, not x
 int launch_tile_horner(const TileArgs &a, int batch, bool c128, void *stream);
+// Whole evolution of small states in one launch (one workgroup per state,
+// the state held in LDS).  Each step part is a list of entries, one per
+// diagonal it applies in order: the diagonal's storage and range, and
+// whether it is the last diagonal of its factor.
+struct WholeEntry {
+    const void *ptr;            // entries of the diagonal, the state's element type
+    int32_t off, lo, hi;        // offset d; rows r with 0 <= r + d < N: [lo, hi)
+    uint32_t last;              // 1 for the last diagonal of a factor
+};
+struct WholeArgs {
+    void *psi;                  // [batch][stride] states of the handle's dtype
+    int64_t stride;
+    int32_t N;
+    int32_t steps;
+    const WholeEntry *walk;     // concatenated entry lists of the step parts
+    int32_t part_off[5];        // part q applies walk[part_off[q] .. part_off[q+1])
+};
+// Largest state (rows) the whole-evolution kernel holds: 8192 complex64 or
+// 4096 complex128 rows (64 KiB of LDS).
+constexpr int kWholeRowsC64 = 8192;
+constexpr int kWholeRowsC128 = 4096;
+int launch_whole(const WholeArgs &a, int batch, bool c128, void *stream);
 // the single-diagonal factor applied `steps` times in one pass (N even)
 int launch_diag_steps(void *y, const void *x, const void *diag, int64_t N, int batch, int steps,
                       const double *nrm2, bool c128, bool stream_out, void *stream);

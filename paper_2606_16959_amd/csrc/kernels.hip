@@ -909,6 +909,157 @@ __global__ __launch_bounds__(NT) void dia_pair_kernel(TileArgs a) {
     if (viol) atomicOr(a.viol, 1);
 }
 
+// ------------------------------------------------------------ whole evolution
+//
+// Small states (at most 8192 complex64 or 4096 complex128 rows): one
+// workgroup per state holds the whole state in LDS and applies every factor
+// of every step in one launch -- no launch per factor run and step, no state
+// traffic between steps.  Thread t owns row pairs (2t + 2 NT p, +1), as the
+// tile kernel's contiguous tiles do; every partner row is in LDS.  Each row
+// sums, per factor, its diagonals in ascending-offset order with the same
+// fused multiply-adds as the tile kernel, starting from zero, so the values
+// are the same as those of one launch per fused run and step.
+//
+// The diagonals are visited in a fixed walk (step s: its part's list of
+// entries).  A ring of KD slots holds the coefficients of the next KD
+// diagonals (KD = 8 / P, so that a thread has about 8 row-pair loads
+// outstanding) with each one's offset and end-of-factor mark: a slot is
+// refilled from the walk KD diagonals ahead of its use, across factor and
+// step boundaries, so using a diagonal reads no table.  The cursor and the
+// walk entries are uniform over the workgroup.
+struct WholeCursor {
+    int s, k, kend;
+    __device__ __forceinline__ static int part_of(const WholeArgs &a, int st) {
+        return a.steps == 1 ? 0 : st == 0 ? 1 : st == a.steps - 1 ? 3 : 2;
+    }
+    __device__ __forceinline__ void start(const WholeArgs &a) {
+        s = 0;
+        const int part = part_of(a, 0);
+        k = a.part_off[part];
+        kend = a.part_off[part + 1];
+    }
+    __device__ __forceinline__ bool done(const WholeArgs &a) const { return s >= a.steps; }
+    __device__ __forceinline__ void next(const WholeArgs &a) {
+        if (++k < kend) return;
+        if (++s < a.steps) {
+            const int part = part_of(a, s);
+            k = a.part_off[part];
+            kend = a.part_off[part + 1];
+        }
+    }
+};
+
+#ifndef HS_WHOLE_KD
+#define HS_WHOLE_KD 8          // row-pair coefficient loads per thread the whole-evolution kernel keeps in flight
+#endif
+
+template <typename R, int P, int NT>
+__global__ __launch_bounds__(NT) void dia_whole_kernel(WholeArgs a) {
+    constexpr int KD = HS_WHOLE_KD / P >= 1 ? HS_WHOLE_KD / P : 1;   // diagonals in flight
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<R> *lds = reinterpret_cast<C2<R> *>(smem_raw);
+    const int N = a.N;
+    const int tid = threadIdx.x;
+    C2<R> *psi = reinterpret_cast<C2<R> *>(a.psi) + (int64_t)blockIdx.x * a.stride;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int i0 = 2 * tid + 2 * NT * p;
+        if (i0 < N) {
+            C2<R> u0, u1;
+            ld2_cached(psi, i0, u0, u1);
+            lds[i0] = u0;
+            lds[i0 + 1] = u1;
+        }
+    }
+    C2<R> c[KD][P][2];
+    int soff[KD];
+    uint32_t slast[KD];
+    WholeCursor fetch;
+    fetch.start(a);
+    // refill slot u with the diagonal at the fetch cursor (zero outside
+    // [lo, hi) and past N; past the walk's end: an empty placeholder)
+    auto refill = [&](int u) {
+        const bool live = !fetch.done(a);
+        const WholeEntry e = a.walk[live ? fetch.k : 0];
+        const C2<R> *cp = reinterpret_cast<const C2<R> *>(e.ptr);
+        const int neg = e.off < 0 ? e.off : 0;
+        const int len = live ? e.hi - e.lo : 0;
+        soff[u] = e.off;
+        slast[u] = e.last;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int ei = i0 + j + neg;
+                const bool ok = ei >= 0 && ei < len && i0 < N;
+                c[u][p][j] = cmask(ld1(cp, ok ? ei : 0), ok);
+            }
+        }
+        if (live) fetch.next(a);
+    };
+#pragma unroll
+    for (int u = 0; u < KD; ++u) refill(u);
+    __syncthreads();
+    C2<R> acc[P][2];
+#pragma unroll
+    for (int p = 0; p < P; ++p) acc[p][0] = acc[p][1] = C2<R>{(R)0, (R)0};
+    // use slot u for the next diagonal of the walk
+    auto consume = [&](int u) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int pr = i0 + j + soff[u];
+                const int sl = (pr >= 0 && pr < N) ? pr : (i0 < N ? i0 + j : 0);
+                cfma(acc[p][j], c[u][p][j], lds[sl]);
+            }
+        }
+    };
+    // the factor is complete: it becomes the state
+    auto end_factor = [&]() {
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int i0 = 2 * tid + 2 * NT * p;
+            if (i0 < N) {
+                lds[i0] = acc[p][0];
+                lds[i0 + 1] = acc[p][1];
+            }
+            acc[p][0] = acc[p][1] = C2<R>{(R)0, (R)0};
+        }
+        __syncthreads();
+    };
+    // the walk's length over all steps; full rounds of KD diagonals refill
+    // every slot (a fixed number of loads per round), the rest only consume
+    auto plen = [&](int q) { return a.part_off[q + 1] - a.part_off[q]; };
+    const int64_t total = a.steps == 1 ? plen(0)
+                                       : (int64_t)plen(1) + (int64_t)(a.steps - 2) * plen(2) + plen(3);
+    int64_t done = 0;
+    for (; done + KD <= total; done += KD) {
+#pragma unroll
+        for (int u = 0; u < KD; ++u) {
+            const bool last = slast[u] != 0;
+            consume(u);
+            refill(u);
+            if (last) end_factor();
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < KD; ++u) {
+        if (done + u < total) {
+            consume(u);
+            if (slast[u] != 0) end_factor();
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int i0 = 2 * tid + 2 * NT * p;
+        if (i0 < N) st2<false>(psi, i0, lds[i0], lds[i0 + 1]);
+    }
+}
+
 // Single main-diagonal factor applied `steps` times: y[i] = v[i]^steps x[i]
 // for N even, each thread two adjacent entries (one 16-byte load of the
 // coefficients and of each state for complex64), the powers taken as
@@ -1186,6 +1337,37 @@ int launch_tile_horner(const TileArgs &a, int batch, bool c128, void *stream) {
     if (!a.x0) return (int)hipErrorInvalidValue;
     return c128 ? tile_dispatch<double>(a, batch, kHorner, stream)
                 : tile_dispatch<float>(a, batch, kHorner, stream);
+}
+
+
+template <typename R, int P, int NT>
+static int whole_launch(const WholeArgs &a, int batch, void *stream) {
+    auto kern = dia_whole_kernel<R, P, NT>;
+    const size_t lds = (size_t)a.N * sizeof(C2<R>);
+    if (lds > 65536) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(kern, dim3(batch), dim3(NT), lds, S(stream), a);
+    return (int)hipGetLastError();
+}
+
+// threads and row pairs per thread for N rows: 2 NT P >= N
+template <typename R>
+static int whole_dispatch(const WholeArgs &a, int batch, void *stream) {
+    const int N = a.N;
+    if (N <= 128) return whole_launch<R, 1, 64>(a, batch, stream);
+    if (N <= 256) return whole_launch<R, 1, 128>(a, batch, stream);
+    if (N <= 512) return whole_launch<R, 1, 256>(a, batch, stream);
+    if (N <= 1024) return whole_launch<R, 1, 512>(a, batch, stream);
+    if (N <= 2048) return whole_launch<R, 2, 512>(a, batch, stream);
+    if (N <= 4096) return whole_launch<R, 4, 512>(a, batch, stream);
+    if constexpr (sizeof(R) == 4) {
+        if (N <= 8192) return whole_launch<R, 8, 512>(a, batch, stream);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+int launch_whole(const WholeArgs &a, int batch, bool c128, void *stream) {
+    if (a.N < 2 || (a.N & 1) || batch < 1 || a.steps < 1 || a.part_off[4] < 1) return (int)hipErrorInvalidValue;
+    return c128 ? whole_dispatch<double>(a, batch, stream) : whole_dispatch<float>(a, batch, stream);
 }
 
 template <typename R, bool STREAM>

@@ -1,4 +1,5 @@
 """Helpers shared by the GPU tests (inputs and oracle runs on the host)."""
+import contextlib
 import os
 import sys
 
@@ -41,3 +42,18 @@ def tol_c64():
 
 def oracle_threads():
     return int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+
+
+@contextlib.contextmanager
+def env(**kw):
+    """Set library environment knobs (read by the library at every call)."""
+    saved = {k: os.environ.get(k) for k in kw}
+    os.environ.update({k: str(v) for k, v in kw.items()})
+    try:
+        yield
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v

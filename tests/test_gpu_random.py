@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from gpu_common import fid, hs_gpu, note, oracle_threads, tol_c64
+from gpu_common import env, fid, hs_gpu, note, oracle_threads, tol_c64
 from oracle import dia as odia, evolve as oev, factors as ofac, pauli as opauli, spme as ospme, taylor as otay
 from workloads import hamiltonians as wh
 
@@ -81,6 +81,17 @@ def _trotter_case(c, seed):
     p = torch.from_numpy(psi0.copy()).cuda()
     hs.evolve(f, p, c["steps"], renorm=c["renorm"])
     got = p.cpu().numpy().astype(np.complex128)
+    if not c["renorm"] and (1 << c["n"]) <= (4096 if c["dtype"] == "c128" else 8192):
+        # small states: the whole evolution in one launch (the cap raised to
+        # the kernel's capacity) and the launch per run and step give the
+        # same values
+        q = torch.from_numpy(psi0.copy()).cuda()
+        w = torch.from_numpy(psi0.copy()).cuda()
+        with env(HAMSIM_WHOLE_MAX_ROWS=0):
+            hs.evolve(f, q, c["steps"])
+        with env(HAMSIM_WHOLE_MAX_ROWS=8192):
+            hs.evolve(f, w, c["steps"])
+        assert np.array_equal(q.cpu().numpy(), w.cpu().numpy())
     assert f.check_closure()
     f.close()
     start = psi0.astype(np.complex128)
