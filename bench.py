@@ -200,7 +200,7 @@ def serve_leg(torch, n_jobs, rate, slots, oracle_nmax):
     return st
 
 
-def summarize_profiles(trace_dir, fetch_dir, write_dir, command):
+def summarize_profiles(trace_dir, fetch_dir, write_dir, command, extra_dirs=()):
     """Turn rocprofv3 CSV output of bench.py runs into the committed summaries:
     per-kernel durations (trace) and per-launch HBM bytes of the DIA tile
     kernel from FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each scaled by
@@ -217,7 +217,7 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, command):
 
     stats = rows(trace_dir, "*kernel_stats.csv")
     trace = sorted(rows(trace_dir, "*kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
-    tile = [r for r in trace if "dia_tile_kernel" in r["Kernel_Name"]]
+    tile = [r for r in trace if _step_kernel(r["Kernel_Name"])]
     os.makedirs(OUT_DIR, exist_ok=True)
     md = ["# dia_tile_kernel on tfim2d 5x5 + ancilla, n=26, complex64, budget 16", "",
           "Command (repository root, on the MI355X):", "", "```", command, "```", "",
@@ -238,8 +238,8 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, command):
     expected_kib = (1 << 31) / 1024.0
     f_scale = expected_kib / (sorted(fcopy)[-1] if fcopy else expected_kib)
     w_scale = expected_kib / big if big else 1.0
-    ft = [float(r["Counter_Value"]) for r in fetch if "dia_tile_kernel" in r["Kernel_Name"]]
-    wt = [float(r["Counter_Value"]) for r in write if "dia_tile_kernel" in r["Kernel_Name"]]
+    ft = [float(r["Counter_Value"]) for r in fetch if _step_kernel(r["Kernel_Name"])]
+    wt = [float(r["Counter_Value"]) for r in write if _step_kernel(r["Kernel_Name"])]
     nl = 3
     per = []
     for j in range(nl):
@@ -249,14 +249,42 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, command):
     durs = [[] for _ in range(nl)]
     for i, r in enumerate(tile):
         durs[i % nl].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
-    md += ["", "## HBM traffic of dia_tile_kernel per launch position in a step", "",
+    reqc = {}
+    for d in extra_dirs:
+        rs = sorted(rows(d, "*counter_collection.csv"), key=lambda r: int(r["Dispatch_Id"]))
+        for name in {r["Counter_Name"] for r in rs}:
+            reqc[name] = [float(r["Counter_Value"]) for r in rs
+                          if r["Counter_Name"] == name and _step_kernel(r["Kernel_Name"])]
+            cp = [float(r["Counter_Value"]) for r in rs if r["Counter_Name"] == name and "copyBuffer" in r["Kernel_Name"]]
+            reqc["copy:" + name] = [max(cp)] if cp else []
+    forms = [("pair" if "dia_pair_kernel" in r["Kernel_Name"] else "row") for r in tile[:nl]]
+    md += ["", "## HBM traffic of the DIA tile kernel per launch position in a step", "",
            f"Copy calibration: a 2 GiB device copy reads {sorted(fcopy)[-1] if fcopy else 0:.0f} KiB "
            f"(FETCH_SIZE) and writes {big:.0f} KiB (WRITE_SIZE); scale factors {f_scale:.4f} "
-           f"and {w_scale:.4f}.", "",
-           "| launch | avg ms | FETCH KiB | WRITE KiB | scaled GB |", "|---|---|---|---|---|"]
+           f"and {w_scale:.4f}.", ""]
+    req_ok = request_bytes(reqc, 0, nl) is not None
+    hdr = "| launch | kernel form | avg ms | FETCH KiB | WRITE KiB | scaled GB |"
+    if req_ok:
+        hdr += " request-size GB |"
+    md += [hdr, "|" + "---|" * (hdr.count("|") - 1)]
     for j in range(nl):
-        md.append(f"| {j} | {sum(durs[j]) / max(1, len(durs[j])):.3f} | {sum(ft[j::nl]) / len(ft[j::nl]):.0f} | "
-                  f"{sum(wt[j::nl]) / len(wt[j::nl]):.0f} | {per[j] / 1e9:.3f} |")
+        line = (f"| {j} | {forms[j]} | {sum(durs[j]) / max(1, len(durs[j])):.3f} | {sum(ft[j::nl]) / len(ft[j::nl]):.0f} | "
+                f"{sum(wt[j::nl]) / len(wt[j::nl]):.0f} | {per[j] / 1e9:.3f} |")
+        if req_ok:
+            rd, wr = request_bytes(reqc, j, nl)
+            line += f" {(rd + (wr or 0)) / 1e9:.3f} |"
+        md.append(line)
+    if req_ok:
+        cr = {k[5:]: v for k, v in reqc.items() if k.startswith("copy:")}
+        crd = request_bytes(cr)
+        md += ["", "Request-size bytes (128 TCC_EA0_RDREQ_128B + 64 TCC_EA0_RDREQ_64B + 32 TCC_EA0_RDREQ_32B read, "
+               "64 TCC_EA0_WRREQ_64B + 32 (TCC_EA0_WRREQ - TCC_EA0_WRREQ_64B) written) need no calibration: "
+               + (f"for the 2 GiB copy they give {crd[0] / 2**30:.3f} GiB read and {(crd[1] or 0) / 2**30:.3f} GiB "
+                  "written. " if crd else "")
+               + "FETCH_SIZE's formula counts each request that is neither a bubble nor 32 bytes as 64 bytes, so "
+               "on 128-byte requests it reads half the bytes: the copy calibration's factor 2."]
+    md += ["", f"Average over the {nl} launches of a step: "
+           f"{float(np.mean([sum(x) / max(1, len(x)) for x in durs])):.4f} ms per launch."]
     with open(os.path.join(OUT_DIR, "dia_tile_tfim2d_n26.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
     with open(os.path.join(OUT_DIR, os.path.basename(TRAFFIC_FILE)), "w") as fh:
@@ -668,6 +696,32 @@ def one_workload_leg(torch, name, dtype, steps=5, warmup=2, batch=None):
             "frac_of_peak": round(sum(per) / ms / 1e6 / HBM_PEAK_GBS, 4)}
 
 
+def _step_kernel(name):
+    """The DIA tile kernel in either form (row by row, or the pair form of
+    closed complex64 launches whose diagonals all pair)."""
+    return "dia_tile_kernel" in name or "dia_pair_kernel" in name
+
+
+def request_bytes(counters, j=None, L=1):
+    """HBM bytes from the request-size counters of the L2 (TCC) to memory:
+    reads 128 / 64 / 32 bytes per request by size class, writes 64 or 32.
+    `counters` maps counter name -> per-dispatch values; j selects every L-th
+    dispatch from position j.  Returns (read bytes, write bytes) or None."""
+    def m(c):
+        v = counters.get(c)
+        if not v:
+            return None
+        v = v[j::L] if j is not None else v
+        return float(np.mean(v)) if v else None
+    r128, r64, r32 = m("TCC_EA0_RDREQ_128B_sum"), m("TCC_EA0_RDREQ_64B_sum"), m("TCC_EA0_RDREQ_32B_sum")
+    w, w64 = m("TCC_EA0_WRREQ_sum"), m("TCC_EA0_WRREQ_64B_sum")
+    if None in (r128, r64, r32):
+        return None
+    rd = 128 * r128 + 64 * r64 + 32 * r32
+    wr = None if None in (w, w64) else 64 * w64 + 32 * (w - w64)
+    return rd, wr
+
+
 def _csv_rows(d, pattern):
     import csv
     import glob
@@ -695,8 +749,9 @@ def summarize_leg_profiles(leg_output, trace_dir, counter_dirs, out_name, comman
         raise SystemExit(f"no leg output in {leg_output}")
     L = leg["launches_per_step"]
     alg = leg["algorithmic_bytes_per_launch"]
-    trace = sorted((r for r in _csv_rows(trace_dir, "*kernel_trace.csv") if "dia_tile_kernel" in r["Kernel_Name"]),
+    trace = sorted((r for r in _csv_rows(trace_dir, "*kernel_trace.csv") if _step_kernel(r["Kernel_Name"])),
                    key=lambda r: int(r["Dispatch_Id"]))
+    forms = [("pair" if "dia_pair_kernel" in r["Kernel_Name"] else "row") for r in trace[-L:]]
     durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in trace]
     if len(durs) % L:
         raise SystemExit(f"{len(durs)} tile dispatches is not a multiple of {L} launches per step")
@@ -707,7 +762,7 @@ def summarize_leg_profiles(leg_output, trace_dir, counter_dirs, out_name, comman
         rows = sorted(_csv_rows(d, "*counter_collection.csv"), key=lambda r: int(r["Dispatch_Id"]))
         for name in sorted({r["Counter_Name"] for r in rows}):
             mine = [r for r in rows if r["Counter_Name"] == name]
-            counters[name] = [float(r["Counter_Value"]) for r in mine if "dia_tile_kernel" in r["Kernel_Name"]]
+            counters[name] = [float(r["Counter_Value"]) for r in mine if _step_kernel(r["Kernel_Name"])]
             cp = [float(r["Counter_Value"]) for r in mine if "copyBuffer" in r["Kernel_Name"]]
             if cp:
                 copy_val[name] = max(cp)
@@ -717,7 +772,7 @@ def summarize_leg_profiles(leg_output, trace_dir, counter_dirs, out_name, comman
           f"Leg: {leg['warmup']} warm-up + {leg['steps']} timed Trotter steps; {L} launches per step "
           f"(factors per launch {leg['launch_factors']}); {leg['ms_per_step']} ms/step from HIP events, "
           f"{leg['gb_per_step']} algorithmic GB/step, {leg['gbs']} GB/s = {100 * leg['frac_of_peak']:.1f}% of 8 TB/s.", ""]
-    hdr = ["launch", "avg ms (trace)", "algorithmic GB", "algorithmic GB/s"]
+    hdr = ["launch", "kernel form", "avg ms (trace)", "algorithmic GB", "algorithmic GB/s"]
     scaled = {}
     for cname in ("FETCH_SIZE", "WRITE_SIZE"):
         if cname in counters and copy_val.get(cname):
@@ -727,17 +782,36 @@ def summarize_leg_profiles(leg_output, trace_dir, counter_dirs, out_name, comman
                ", ".join(f"{c} reads {copy_val[c]:.0f} KiB, scale {s:.4f}" for c, s in scaled.items()), ""]
         hdr += ["HBM GB (scaled FETCH + WRITE)", "HBM / algorithmic"]
     other = [c for c in sorted(counters) if c not in ("FETCH_SIZE", "WRITE_SIZE")]
+    req = request_bytes(counters, 0, L) is not None
+    reads_only = req and request_bytes(counters, 0, L)[1] is None
+    wbytes = leg["batch"] * (1 << leg["n"]) * (16 if leg["dtype"] == "c128" else 8)   # the states written once
+    if req:
+        hdr += (["HBM read GB (request sizes)", "read / algorithmic read"] if reads_only
+                else ["HBM GB (request sizes)", "request / algorithmic"])
     hdr += other
     md += ["| " + " | ".join(hdr) + " |", "|" + "---|" * len(hdr)]
     for j in range(L):
-        row = [str(j), f"{pos_ms[j]:.4f}", f"{alg[j] / 1e9:.3f}", f"{alg[j] / pos_ms[j] / 1e6:.0f}"]
+        row = [str(j), forms[j], f"{pos_ms[j]:.4f}", f"{alg[j] / 1e9:.3f}", f"{alg[j] / pos_ms[j] / 1e6:.0f}"]
         if scaled:
             hb = sum(float(np.mean(counters[c][j::L])) * s * 1024 for c, s in scaled.items())
             row += [f"{hb / 1e9:.3f}", f"{hb / alg[j]:.3f}"]
+        if req:
+            rd, wr = request_bytes(counters, j, L)
+            if reads_only:
+                row += [f"{rd / 1e9:.3f}", f"{rd / (alg[j] - wbytes):.3f}"]
+            else:
+                row += [f"{(rd + wr) / 1e9:.3f}", f"{(rd + wr) / alg[j]:.3f}"]
         for c in other:
             v = counters[c][j::L]
             row.append(f"{float(np.mean(v)):.4g}" if v else "-")
         md.append("| " + " | ".join(row) + " |")
+    if req:
+        md += ["", "Request sizes: read bytes = 128 TCC_EA0_RDREQ_128B + 64 TCC_EA0_RDREQ_64B + 32 TCC_EA0_RDREQ_32B, "
+               "write bytes = 64 TCC_EA0_WRREQ_64B + 32 (TCC_EA0_WRREQ - TCC_EA0_WRREQ_64B), summed over the L2 "
+               "channels.  FETCH_SIZE's formula counts every request that is neither a bubble nor 32 bytes as 64 "
+               "bytes, so on 128-byte requests it reads half the bytes (the copy calibration's factor 2)."]
+    md += ["", f"Average over the {L} launches of a step: {float(np.mean(pos_ms)):.4f} ms per launch, "
+           f"{sum(alg) / len(alg) / 1e9:.3f} algorithmic GB per launch."]
     stats = _csv_rows(trace_dir, "*kernel_stats.csv")
     md += ["", "## rocprofv3 --kernel-trace --stats", "",
            "| kernel | calls | avg us | min us | max us | % |", "|---|---|---|---|---|---|"]
@@ -746,6 +820,61 @@ def summarize_leg_profiles(leg_output, trace_dir, counter_dirs, out_name, comman
                   f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
     os.makedirs(OUT_DIR, exist_ok=True)
     with open(os.path.join(OUT_DIR, out_name), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
+def summarize_diagonal_profiles(leg_output, trace_dir, fetch_dir, write_dir, command):
+    """Profile summary of `bench.py --leg diagonal`: the single-diagonal
+    kernel's dispatches in order (one warm-up pass, the timed one-step passes,
+    then the whole run in one pass), with FETCH_SIZE / WRITE_SIZE scaled by
+    the copy calibration stored with the tile kernel's traffic summary."""
+    leg = None
+    with open(leg_output) as fh:
+        for line in fh:
+            if line.startswith('{"leg"'):
+                leg = json.loads(line)["result"]
+    if leg is None:
+        raise SystemExit(f"no diagonal leg output in {leg_output}")
+    with open(TRAFFIC_FILE) as fh:
+        cal = json.load(fh)
+
+    def disp(d, cname=None):
+        rs = _csv_rows(d, "*counter_collection.csv" if cname else "*kernel_trace.csv")
+        rs = [r for r in rs if "diag_steps_kernel" in r["Kernel_Name"] and (not cname or r["Counter_Name"] == cname)]
+        rs.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return rs
+    tr = disp(trace_dir)
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in tr]
+    fe = [float(r["Counter_Value"]) for r in disp(fetch_dir, "FETCH_SIZE")]
+    wr = [float(r["Counter_Value"]) for r in disp(write_dir, "WRITE_SIZE")]
+    nb = leg["gb_per_pass"] * 1e9
+    n1 = len(durs) - 1                       # the last dispatch is the whole run in one pass
+    groups = [("one step per pass", slice(1, n1)), (f"all {leg['all_steps_one_pass']['steps']} steps in one pass",
+                                                    slice(n1, n1 + 1))]
+    md = [f"# diag_steps_kernel: {leg['workload']}, n={leg['n']}, {leg['dtype']}, one state", "",
+          "Command (repository root, on the MI355X):", "", "```", command, "```", "",
+          f"A step of a diagonal Hamiltonian is one diagonal factor; algorithmic bytes per pass: the diagonal once "
+          f"and the state read and written, {leg['gb_per_pass']} GB.  FETCH_SIZE is scaled by "
+          f"{cal['fetch_scale']:.4f} and WRITE_SIZE by {cal['write_scale']:.4f} (the copy calibration of "
+          f"`{os.path.relpath(TRAFFIC_FILE, ROOT)}`).", "",
+          "| dispatches | avg ms | algorithmic GB/s | % of 8 TB/s | HBM GB (scaled FETCH + WRITE) | HBM / algorithmic |",
+          "|---|---|---|---|---|---|"]
+    for name, sl in groups:
+        d, f, w = durs[sl], fe[sl], wr[sl]
+        ms = float(np.mean(d))
+        hb = (float(np.mean(f)) * cal["fetch_scale"] + float(np.mean(w)) * cal["write_scale"]) * 1024
+        md.append(f"| {name} ({len(d)}) | {ms:.4f} | {nb / ms / 1e6:.0f} | {100 * nb / ms / 1e6 / HBM_PEAK_GBS:.1f} | "
+                  f"{hb / 1e9:.3f} | {hb / nb:.3f} |")
+    steps = leg["all_steps_one_pass"]["steps"]
+    ms_all = durs[n1]
+    flops = 8.0 * steps * (1 << leg["n"])
+    md += ["", f"The pass of {steps} steps multiplies each entry {steps} times in registers (the same "
+           f"multiplications as {steps} passes, so the same bits): {flops / ms_all / 1e9:.1f} TFLOP/s of FP32 "
+           f"complex products ({8 * steps} flops per entry), {100 * flops / ms_all / 1e9 / 78.6:.0f}% of the "
+           "78.6 TFLOP/s of non-packed FP32 FMA (half the 157.3 TFLOP/s vector peak, which counts packed "
+           "operations): it is bound by the FMA chain, not by HBM."]
+    with open(os.path.join(OUT_DIR, "diag_steps_maxcut_cost_n26.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
     print("\n".join(md))
 
@@ -919,13 +1048,15 @@ def main():
     ap.add_argument("--workload", default="maxcut_3reg_n24", help="named workload of --leg workload")
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128"], help="dtype of --leg workload")
     ap.add_argument("--batch", type=int, default=0, help="states of --leg workload (0 = the workload's)")
+    ap.add_argument("--summarize-diagonal-profiles", nargs=4, metavar=("LEG_OUTPUT", "TRACE", "FETCH", "WRITE"),
+                    help="profile summary of a --leg diagonal run")
     ap.add_argument("--summarize-leg-profiles", nargs="+", metavar="DIR",
                     help="LEG_OUTPUT TRACE COUNTER_DIR... : per-launch summary of a --leg workload run")
     ap.add_argument("--summary-name", default="", help="file name under profiles/ of --summarize-leg-profiles")
     ap.add_argument("--no-other-workloads", action="store_true")
     ap.add_argument("--serve-sweep", default="", help="comma-separated arrival rates (jobs/s)")
-    ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
-                    help="write profiles/ summaries from rocprofv3 output directories")
+    ap.add_argument("--summarize-profiles", nargs="+", metavar="DIR",
+                    help="TRACE FETCH WRITE [REQUEST_COUNTER_DIR...]: write profiles/ summaries from rocprofv3 output")
     ap.add_argument("--profile-command", default="")
     ap.add_argument("--summarize-taylor-profiles", nargs=4, metavar=("TRACE", "FETCH", "WRITE", "LEG_OUTPUT"),
                     help="write the fused Taylor update's profile summary from rocprofv3 output directories")
@@ -937,10 +1068,14 @@ def main():
         OUT_DIR = os.path.abspath(args.out_dir)
         os.makedirs(OUT_DIR, exist_ok=True)
     if args.summarize_profiles:
-        summarize_profiles(*args.summarize_profiles, args.profile_command)
+        tr, fe, wr, *extra = args.summarize_profiles
+        summarize_profiles(tr, fe, wr, args.profile_command, extra)
         return
     if args.summarize_taylor_profiles:
         summarize_taylor_profiles(*args.summarize_taylor_profiles)
+        return
+    if args.summarize_diagonal_profiles:
+        summarize_diagonal_profiles(*args.summarize_diagonal_profiles, args.profile_command)
         return
     if args.summarize_leg_profiles:
         lo, tr, *cdirs = args.summarize_leg_profiles
@@ -1028,7 +1163,8 @@ def main():
     achieved = avg_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(per_launch, len(launches)),
-            "kernel": "dia_tile_kernel (complex64, batch 1, closed tiles)",
+            "kernel": "DIA tile kernel (complex64, one state, closed tiles; row form, pair form where every "
+                      "diagonal pairs)",
             "algorithmic_bytes_per_launch": [int(b) for b in per_launch],
             "avg_launch_ms": round(avg_launch_ms, 4)}
 
