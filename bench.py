@@ -161,11 +161,12 @@ def accuracy(got, ref):
             "max_norm_drift": float(np.max(np.abs(np.linalg.norm(g, axis=1) - 1.0)))}
 
 
-def serve_leg(torch, n_jobs, rate, slots, oracle_nmax):
+def serve_leg(torch, n_jobs, rate, slots, oracle_nmax, jsonl_dir=None):
     """Served stream (seeded Poisson arrivals of mixed-family jobs) and the
     oracle check of a 5% sample (jobs whose id hashes into the sample and
     whose n <= oracle_nmax, every n by default; state column 0, the whole run
-    of the job, after the stream)."""
+    of the job, after the stream).  With jsonl_dir, every job's record is
+    appended to serve_<jobs>jobs_<rate>per_s.jsonl there."""
     from oracle import evolve as oev, factors as ofac, metrics, pauli as opauli
     from paper_2606_16959_amd.serve import Job, Server
     from workloads.serve_stream import job_stream
@@ -179,7 +180,11 @@ def serve_leg(torch, n_jobs, rate, slots, oracle_nmax):
                         arrival=sp.arrival, keep_result=sp.job_id in sample and sp.n <= oracle_nmax,
                         tag=sp.family))
     log(f"serve: {n_jobs} jobs at {rate}/s on {slots} slots")
-    res, st = Server(slots=slots).run(jobs)
+    jsonl = None
+    if jsonl_dir:
+        os.makedirs(jsonl_dir, exist_ok=True)
+        jsonl = os.path.join(jsonl_dir, f"serve_{n_jobs}jobs_{rate:g}per_s.jsonl")
+    res, st = Server(slots=slots).run(jobs, jsonl=jsonl)
     log(f"serve: p50 {st['latency_ms']['p50']:.1f} ms p99 {st['latency_ms']['p99']:.1f} ms "
         f"{st['throughput_jobs_s']:.1f} jobs/s")
     worst, checked, t_or = 1.0, 0, time.perf_counter()
@@ -970,7 +975,8 @@ def write_serve_summary(stats, command, fname):
           f"Command (repository root, on the MI355X): `{command}`", "",
           "Latency = arrival -> completion event of the job's last kernel; queue wait = arrival -> "
           "admission; service = admission -> completion (factor build + state setup + evolution). "
-          "Oracle check: jobs hashed into a 5% sample with n <= 16, state column 0, FP64 oracle.", "",
+          f"Oracle check: jobs hashed into a 5% sample with n <= {stats[0]['oracle_nmax']} (every n of the "
+          "stream), state column 0, whole run, FP64 oracle.", "",
           "| jobs | rate (jobs/s) | completed | p50 ms | p99 ms | max ms | queue p50 ms | service p50 ms | "
           "service p99 ms | throughput jobs/s | device busy | peak active | oracle checked | min fidelity |",
           "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
@@ -1055,6 +1061,7 @@ def main():
     ap.add_argument("--summary-name", default="", help="file name under profiles/ of --summarize-leg-profiles")
     ap.add_argument("--no-other-workloads", action="store_true")
     ap.add_argument("--serve-sweep", default="", help="comma-separated arrival rates (jobs/s)")
+    ap.add_argument("--serve-jsonl", default=None, help="directory for per-job JSONL records of served streams")
     ap.add_argument("--summarize-profiles", nargs="+", metavar="DIR",
                     help="TRACE FETCH WRITE [REQUEST_COUNTER_DIR...]: write profiles/ summaries from rocprofv3 output")
     ap.add_argument("--profile-command", default="")
@@ -1103,7 +1110,8 @@ def main():
         print(json.dumps({"leg": args.leg, "result": legs[args.leg](torch)}), flush=True)
         return
     if args.serve_only:
-        st = serve_leg(torch, args.serve_jobs, args.serve_rate, args.serve_slots, args.serve_oracle_nmax)
+        st = serve_leg(torch, args.serve_jobs, args.serve_rate, args.serve_slots, args.serve_oracle_nmax,
+                       args.serve_jsonl)
         print(json.dumps({"metric": "served-solve latency", "serve": st}), flush=True)
         if args.out_dir:
             write_serve_summary([st], f"python3 bench.py --serve-only --serve-jobs {args.serve_jobs} "
@@ -1112,7 +1120,8 @@ def main():
         return
     if args.serve_sweep:
         rates = [float(r) for r in args.serve_sweep.split(",")]
-        sts = [serve_leg(torch, args.serve_jobs, r, args.serve_slots, args.serve_oracle_nmax) for r in rates]
+        sts = [serve_leg(torch, args.serve_jobs, r, args.serve_slots, args.serve_oracle_nmax, args.serve_jsonl)
+               for r in rates]
         write_serve_summary(sts, f"python3 bench.py --serve-sweep {args.serve_sweep} --serve-jobs "
                                  f"{args.serve_jobs} --serve-slots {args.serve_slots}",
                             f"serve_rate_sweep_{args.serve_jobs}jobs.md")
@@ -1212,7 +1221,7 @@ def main():
         f.close()
         torch.cuda.empty_cache()
         serve = serve_leg(torch, args.serve_jobs, args.serve_rate, args.serve_slots,
-                          args.serve_oracle_nmax)
+                          args.serve_oracle_nmax, args.serve_jsonl)
 
     line = {
         "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1,
