@@ -153,7 +153,8 @@ class Server:
         return s
 
     def cancel(self, job_id: int):
-        """Cancel a queued or running job (running: at its next chunk boundary)."""
+        """Cancel a queued or running job of the current or next run (running:
+        at its next chunk boundary); the request is dropped when that run ends."""
         with self._cancel_lock:
             self._cancel.add(job_id)
 
@@ -359,6 +360,8 @@ class Server:
         ex.shutdown(wait=True)
         if out_fh is not None:
             out_fh.close()
+        with self._cancel_lock:             # a cancellation ends with its run
+            self._cancel.difference_update(results.keys())
         out = [results[j.job_id] for j in jobs]
         stats = summarize(out)
         stats.update(peak_hbm_bytes=peak["used"], peak_active=peak["active"], slots=self.slots,

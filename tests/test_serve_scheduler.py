@@ -100,6 +100,9 @@ def test_queued_job_is_cancelled_others_complete(tmp_path):
     assert status == {0: "ok", 1: "ok", 2: "cancelled", 3: "ok", 4: "ok"}
     assert 2 not in s.order
     assert st["completed"] == 4 and st["cancelled"] == 1
+    # the cancellation ended with its run: the same id runs in the next one
+    res, st = s.run(_jobs(5), realtime=False)
+    assert all(r.status == "ok" for r in res) and st["completed"] == 5
 
 
 def test_jsonl_has_one_record_per_job_with_final_status(tmp_path):
