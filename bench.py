@@ -450,10 +450,13 @@ def other_workloads(torch, steps=10, warmup=2, pool=None):
             got = pa.cpu().numpy()
             terms = opauli.parse_terms(H.strings, H.coeffs, H.n)
             part = ofac.first_fit(terms, run["budget"], run["t"] / run["steps"])
-            job = (lambda terms=terms, part=part, psi0=psi0, n=H.n, dt=run["t"] / run["steps"], k=k:
-                   oev.evolve(terms, part, psi0, n, dt, k))
+            job = (lambda terms=terms, part=part, psi0=psi0, n=H.n, dt=run["t"] / run["steps"], k=k, th=0:
+                   oev.evolve(terms, part, psi0, n, dt, k, threads=th))
             if pool is not None and cfg in BACKGROUND_ORACLE:
-                fut = pool.submit(job)
+                # beside the GPU legs: leave two host cores to the thread that
+                # enqueues their launches (with every core busy, legs of short
+                # launches measured up to 20% slower)
+                fut = pool.submit(job, th=max(1, oev.max_threads() - 2))
                 row["accuracy_vs_oracle"] = ("pending", fut, got, k)
             else:
                 if cfg not in oracle_refs:
