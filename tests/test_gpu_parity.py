@@ -315,18 +315,20 @@ def _maxcut_cost(n, seed):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-def test_diagonal_steps_in_one_pass_equal_step_by_step(dtype):
+@pytest.mark.parametrize("batch", [1, 3])
+def test_diagonal_steps_in_one_pass_equal_step_by_step(dtype, batch):
     """A diagonal Hamiltonian's step is one diagonal factor; without
     renormalisation the library applies all steps in one pass.  That pass
-    equals one call per step bit for bit (batch of 3), and with
-    renormalisation (step by step) it stays within rounding of it."""
+    equals one call per step, and two calls of 11 and 26 steps, bit for bit
+    (one and three states), and with renormalisation (step by step) it stays
+    within rounding of it."""
     hs, torch = hs_gpu()
     H = _maxcut_cost(16, 9)
     npd = np.complex128 if dtype == "c128" else np.complex64
-    note(f"diagonal steps one pass vs step by step {dtype}")
+    note(f"diagonal steps one pass vs step by step {dtype} batch {batch}")
     f = hs.build_factors(H.strings, H.coeffs, 16, 1.0, 37, 16, dtype=dtype)
     assert f.n_factors == 1 and f.describe()["factors"][0]["offsets"] == [0]
-    psi0 = np.stack([ws.random_phase_state(16, s, npd) for s in (1, 2, 3)])
+    psi0 = np.stack([ws.random_phase_state(16, s, npd) for s in (1, 2, 3)[:batch]])
     a = _to_dev(torch, psi0, npd)
     hs.evolve(f, a, 37)
     b = _to_dev(torch, psi0, npd)
