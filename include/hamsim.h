@@ -185,6 +185,20 @@ hs_status hs_factor_offsets(hs_factors f, int k, long long *offsets, int cap);
  * host memory; synchronises `stream`. */
 hs_status hs_factor_copy_diagonal(hs_factors f, int k, int j, long long start, long long count,
                                   void *host_dst, void *stream);
+/* Storage order of factor k's diagonals in device memory (the values are the
+ * same in every order; hs_factor_copy_diagonal always returns natural
+ * order).  Eq. 6 stores the coefficient A[r, r + d] of diagonal d at index
+ * i = min(r, r + d).  With *split_bit = s > 0 and *chunk_bits = c, entry i
+ * sits instead at
+ *   ((i mod 2^s) >> c) * ((N - |d|) >> s << c) + (i >> s << c) + (i mod 2^c):
+ * runs of 2^c entries, all values of i >> s of one run column one after the
+ * other, so that a tile holding every level of bits [s, ...) for a window of
+ * low rows reads one short stretch per column instead of one run per level
+ * 2^s entries apart.  Each diagonal still holds exactly N - |d| entries.
+ * The library chooses it at build for factors applied in strided tiles whose
+ * levels lie at least HAMSIM_PERM_MIN_BYTES apart; s = c = 0 is the natural
+ * order.  Either output may be null. */
+hs_status hs_factor_storage(hs_factors f, int k, int *split_bit, int *chunk_bits);
 /* Bytes of device memory an evolution of `batch` states needs: the stored
  * diagonals (Eq. 6: N - |d| entries per diagonal, each start aligned to 256
  * bytes), the caller's states and the library's workspace (the scratch state

@@ -98,9 +98,12 @@ class Factors:
             _lib.check(lib.hs_factor_offsets(self._h, k, offs, nd.value))
             h = ctypes.c_double()
             _lib.check(lib.hs_factor_step(self._h, k, h))
+            ps, pc = ctypes.c_int(), ctypes.c_int()
+            _lib.check(lib.hs_factor_storage(self._h, k, ps, pc))
             out["factors"].append({"has_diag": bool(hd.value), "terms": list(terms)[: ng.value],
                                    "offsets": list(offs), "support_mask": sm.value,
-                                   "bytes": nb.value, "dt": h.value})
+                                   "bytes": nb.value, "dt": h.value,
+                                   "storage": (ps.value, pc.value)})
         ln = ctypes.c_int()
         _lib.check(lib.hs_step_sequence(self._h, None, 0, ln))
         seq = (ctypes.c_int * max(1, ln.value))()

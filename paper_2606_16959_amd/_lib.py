@@ -36,6 +36,7 @@ _SIG = {
     "hs_factor_step": (_I, [_P, _I, ctypes.POINTER(_D)]),
     "hs_factor_offsets": (_I, [_P, _I, _P, _I]),
     "hs_factor_copy_diagonal": (_I, [_P, _I, _I, _LL, _LL, _P, _P]),
+    "hs_factor_storage": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "hs_step_launches": (_I, [_P, _I, ctypes.c_uint, _I, ctypes.POINTER(_I), _P, _P, _I]),
     "hs_step_joint": (_I, [_P, ctypes.POINTER(_I)]),
     "hs_footprint": (_I, [_P, _I, ctypes.POINTER(ctypes.c_size_t)]),

@@ -100,6 +100,7 @@ struct Run {
     bool pairs = false;         // closed complex64 launch whose every diagonal pairs: the
                                 // partners of a thread's two rows are adjacent, even-aligned
                                 // LDS entries (regular offset, and W even or the offset even)
+    bool perm = false;          // some diagonal is stored out of natural order (perm_pos)
     int desc_start = 0;
     std::vector<int> dstart;    // per factor, relative to desc_start (size nf + 1)
 };
@@ -151,6 +152,7 @@ struct hs_factors_s {
     std::vector<hs::WholeEntry> whole_walk;
     int32_t whole_part_off[5] = {0, 0, 0, 0, 0};
     hs::WholeEntry *whole_walk_dev = nullptr;
+    bool any_perm = false;           // a factor is stored out of natural order (perm_pos)
 
     double *partials() { return work_dev; }
     double *records() { return work_dev + (size_t)HS_MAX_BATCH * hs::kReduceBlocks * 4; }
@@ -172,16 +174,16 @@ struct hs_factors_s {
 
 namespace {
 
-// Greedy fusion: extend a run while the union of coupling hulls still fits
-// one closed tile with rows runs of at least w_min elements.
-hs_status make_evolve_plan(hs_factors_s *h, const PlanKey &key, EvolvePlan &ep, void *stream) {
-    const Plan &P = h->plan;
+// The launches of every step part (host only): greedy fusion extends a run
+// while the union of coupling hulls still fits one closed tile with rows runs
+// of at least w_min elements; each run gets its tile geometry and kernel form.
+void form_runs(const Plan &P, int dtype, const PlanKey &key, EvolvePlan &ep) {
     const int n = P.n;
     const int batch = key.chunk;
     const bool fuse = key.fuse != 0;
-    const int Tmax = tile_rows_max(h->dtype, batch, P.N);
-    const int Wmin = w_min(h->dtype, key);
-    const size_t sc = elem_bytes(h->dtype);
+    const int Tmax = tile_rows_max(dtype, batch, P.N);
+    const int Wmin = w_min(dtype, key);
+    const size_t sc = elem_bytes(dtype);
     ep = EvolvePlan();
     ep.swizzle = key.swizzle;
     const int max_fuse = key.max_fuse;
@@ -224,21 +226,81 @@ hs_status make_evolve_plan(hs_factors_s *h, const PlanKey &key, EvolvePlan &ep, 
             run.geo = geometry(empty ? 0 : lb, empty ? 0 : hb, n, Tmax);
             if (!run.geo.ok) {            // orbit wider than the batched tile: one state per launch
                 run.launch_batch = 1;
-                run.geo = geometry(lb, hb, n, tile_rows_max(h->dtype, 1, P.N));
+                run.geo = geometry(lb, hb, n, tile_rows_max(dtype, 1, P.N));
             }
             if (!run.geo.ok) {            // no closed tile at all (a single factor): open launch
                 const Factor &Fo = P.factors[run.factors[0]];
                 std::vector<long long> o(Fo.offs.begin(), Fo.offs.end());
                 run.launch_batch = batch;
-                run.geo = generic_geometry(o.data(), (int)o.size(), P.N, h->dtype, batch);
+                run.geo = generic_geometry(o.data(), (int)o.size(), P.N, dtype, batch);
                 run.open = true;
                 ep.needs_scratch = true;
             }
-            run.desc_start = (int)ep.host_desc.size();
-            run.dstart.push_back(0);
-            run.pairs = key.pairs && h->dtype == HS_C64 && !run.open && !run.elementwise;
+            run.pairs = key.pairs && dtype == HS_C64 && !run.open && !run.elementwise;
             if (key.pairs == 1 && run.geo.qb > 0 && run.launch_batch == 1 && ((size_t)1 << run.geo.logW) * sc < 1024)
                 run.pairs = false;
+            const int64_t lowmask = (int64_t(1) << run.geo.qb) - 1;
+            for (int k : run.factors)
+                for (int64_t d : P.factors[k].offs)
+                    if ((d & lowmask) != 0 || (run.geo.logW == 0 && (d & 1))) run.pairs = false;
+            runs.push_back(run);
+            f = g;
+        }
+    }
+    for (int part = 1; P.joint < 0 && part < kParts; ++part) ep.runs[part] = ep.runs[0];
+}
+
+// Storage order of every factor (perm_pos): a factor that the one-state plan
+// (default fusion) applies only in closed strided launches, whose level stride
+// 2^qb rows spans at least HAMSIM_PERM_MIN_BYTES (default 1 MiB, where every
+// level of a tile lands on its own 2 MB page; 0: never), is stored with
+// s = qb (the smallest over its launches) and chunks of
+// HAMSIM_PERM_CHUNK_BYTES (default 256).  Launches of other batch sizes read
+// the same storage; their tiles keep page locality while their qb is near s.
+void choose_storage_order(Plan &P, int dtype) {
+    for (auto &f : P.factors) f.perm_s = f.perm_c = 0;
+    const int min_bytes = env_int("HAMSIM_PERM_MIN_BYTES", 1 << 20, 0, 1 << 30);
+    if (min_bytes == 0) return;
+    const size_t sc = elem_bytes(dtype);
+    const int chunk_bytes = env_int("HAMSIM_PERM_CHUNK_BYTES", 256, 16, 1 << 20);
+    const int c = ilog2(std::max<int64_t>(2, (int64_t)chunk_bytes / (int64_t)sc));   // >= 2 entries: pairs
+    EvolvePlan ep;
+    form_runs(P, dtype, plan_key(1, true), ep);
+    std::vector<int> smin(P.factors.size(), -1);
+    for (int part = 0; part < kParts; ++part)
+        for (const Run &run : ep.runs[part]) {
+            const bool strided = !run.open && !run.elementwise && run.geo.qb > 0;
+            for (int k : run.factors) {
+                const int q = strided ? run.geo.qb : 0;
+                smin[k] = smin[k] < 0 ? q : std::min(smin[k], q);
+            }
+        }
+    for (size_t k = 0; k < P.factors.size(); ++k) {
+        Factor &F = P.factors[k];
+        const int q = smin[k];
+        if (q <= 0 || q < c || q > 30 || ((size_t)1 << q) * sc < (size_t)min_bytes) continue;
+        bool multiple = true;
+        for (int64_t d : F.offs) multiple = multiple && ((d < 0 ? -d : d) & ((int64_t(1) << q) - 1)) == 0;
+        if (!multiple) continue;
+        F.perm_s = q;
+        F.perm_c = c;
+    }
+}
+
+// The runs of one plan key with their descriptors on the device.
+hs_status make_evolve_plan(hs_factors_s *h, const PlanKey &key, EvolvePlan &ep, void *stream) {
+    const Plan &P = h->plan;
+    const size_t sc = elem_bytes(h->dtype);
+    form_runs(P, h->dtype, key, ep);
+    for (int part = 0; part < kParts; ++part) {
+        if (part > 0 && P.joint < 0) {
+            ep.runs[part] = ep.runs[0];
+            continue;
+        }
+        for (Run &run : ep.runs[part]) {
+            run.desc_start = (int)ep.host_desc.size();
+            run.dstart.assign(1, 0);
+            run.perm = false;
             for (int k : run.factors) {
                 const Factor &Fk = P.factors[k];
                 for (size_t j = 0; j < Fk.offs.size(); ++j) {
@@ -251,16 +313,19 @@ hs_status make_evolve_plan(hs_factors_s *h, const PlanKey &key, EvolvePlan &ep, 
                     dd.m = dd.regular ? (int32_t)(d >> run.geo.qb) : 0;
                     dd.lo = (int32_t)std::max<int64_t>(0, -d);
                     dd.hi = (int32_t)std::min<int64_t>(P.N, P.N - d);
-                    if (!dd.regular || (run.geo.logW == 0 && (d & 1))) run.pairs = false;
+                    dd.ps = Fk.perm_s;
+                    dd.pc = Fk.perm_c;
+                    dd.plr = (int32_t)(((P.N - (d < 0 ? -d : d)) >> Fk.perm_s) << Fk.perm_c);
+                    if (Fk.perm_s > 0) run.perm = true;
                     ep.host_desc.push_back(dd);
                 }
                 run.dstart.push_back((int)(ep.host_desc.size() - run.desc_start));
             }
-            runs.push_back(run);
-            f = g;
+            // out-of-order storage is read by closed tile launches only
+            if (run.perm && (run.open || run.elementwise))
+                return fail(HS_EDEVICE, "a factor stored out of natural order in an open or elementwise launch");
         }
     }
-    for (int part = 1; P.joint < 0 && part < kParts; ++part) ep.runs[part] = ep.runs[0];
     const size_t bytes = ep.host_desc.size() * sizeof(DiagDesc);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     HS_HIP(hipMallocAsync(reinterpret_cast<void **>(&ep.dev_desc), std::max<size_t>(bytes, 64), st),
@@ -312,6 +377,7 @@ hs_status launch_run(hs_factors_s *h, const EvolvePlan &ep, const Run &run, void
         a.swizzle = swizzled(ep.swizzle, run.geo) ? 1 : 0;
         a.stream_out = stream_out(chunk, P.N, h->dtype);
         a.pairs = run.pairs ? 1 : 0;
+        a.perm = run.perm ? 1 : 0;
         // partials of state b0 + b at [((b0 + b) * tiles + tile) * 4]
         a.norm_out = norm_partials ? norm_partials + (size_t)b0 * (P.N / run.geo.T) * 4 : nullptr;
         const int nb = std::min(lbatch, chunk - b0);
@@ -406,6 +472,8 @@ static hs_status build_device(hs_factors_s *h, void *stream) {
     HS_HIP(hipGetDevice(&h->device), "hipGetDevice");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     h->alloc_stream = st;
+    choose_storage_order(P, h->dtype);
+    for (auto &f : P.factors) h->any_perm = h->any_perm || f.perm_s > 0;
     for (auto &f : P.factors) {
         hs::layout_factor(f, P.N, sc);
         HS_HIP(hipMallocAsync(&f.dev, f.elems_total * sc, st), "hipMallocAsync(factor diagonals)");
@@ -494,6 +562,8 @@ static hs_status build_device(hs_factors_s *h, void *stream) {
             a.K = 1;
         }
         a.phase = f.has_diag ? phases[f.dt] : nullptr;
+        a.perm_s = f.perm_s;
+        a.perm_c = f.perm_c;
         int le = hs::launch_construct(a, (int)f.offs.size(), P.N, c128, stream);
         if (le) { cleanup(); return hip_fail((hipError_t)le, "construct kernel"); }
     }
@@ -547,7 +617,7 @@ hs_status hs_evolve(hs_factors f, void *psi, int batch, int steps, void *stream,
     int cur_dev = 0;
     HS_HIP(hipGetDevice(&cur_dev), "hipGetDevice");
     if (cur_dev != f->device) return fail(HS_EINVAL, "current device differs from the build device");
-    if (!(flags & (HS_RENORM | HS_NO_FUSE)) && P.N <= whole_max_rows(f->dtype)) {
+    if (!(flags & (HS_RENORM | HS_NO_FUSE)) && P.N <= whole_max_rows(f->dtype) && !f->any_perm) {
         // a small state: the whole evolution of every state in one launch
         if (!f->whole_ready)
             if (hs_status s = make_whole_tables(f, stream)) return s;
@@ -735,9 +805,32 @@ hs_status hs_factor_copy_diagonal(hs_factors f, int k, int j, long long start, l
     if (count == 0) return HS_OK;
     const size_t sc = elem_bytes(f->dtype);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    HS_HIP(hipMemcpyAsync(host_dst, static_cast<char *>(F->dev) + (F->elem_off[j] + (size_t)start) * sc,
-                          (size_t)count * sc, hipMemcpyDeviceToHost, st), "hipMemcpyAsync(diagonal)");
-    HS_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    const char *src = static_cast<const char *>(F->dev) + F->elem_off[j] * sc;
+    if (F->perm_s == 0) {
+        HS_HIP(hipMemcpyAsync(host_dst, src + (size_t)start * sc, (size_t)count * sc, hipMemcpyDeviceToHost, st),
+               "hipMemcpyAsync(diagonal)");
+        HS_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+        return HS_OK;
+    }
+    // stored out of natural order: gather the range into a temporary first
+    void *tmp = nullptr;
+    HS_HIP(hipMallocAsync(&tmp, (size_t)count * sc, st), "hipMallocAsync(diagonal copy)");
+    int e = hs::launch_perm_gather(src, tmp, start, count, len, F->perm_s, F->perm_c, f->dtype == HS_C128, stream);
+    hipError_t he = e ? (hipError_t)e
+                      : hipMemcpyAsync(host_dst, tmp, (size_t)count * sc, hipMemcpyDeviceToHost, st);
+    const hipError_t fe = hipFreeAsync(tmp, st);
+    const hipError_t se = hipStreamSynchronize(st);
+    if (he != hipSuccess) return hip_fail(he, "diagonal gather");
+    if (fe != hipSuccess) return hip_fail(fe, "hipFreeAsync(diagonal copy)");
+    if (se != hipSuccess) return hip_fail(se, "hipStreamSynchronize");
+    return HS_OK;
+}
+
+hs_status hs_factor_storage(hs_factors f, int k, int *split_bit, int *chunk_bits) {
+    const Factor *F = nullptr;
+    if (hs_status s = get_factor(f, k, &F)) return s;
+    if (split_bit) *split_bit = F->perm_s;
+    if (chunk_bits) *chunk_bits = F->perm_c;
     return HS_OK;
 }
 

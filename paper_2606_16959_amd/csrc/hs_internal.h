@@ -34,6 +34,8 @@ struct Factor {
     std::vector<std::complex<double>> L;  // K x K local unitary, row-major
     std::vector<size_t> elem_off;   // element offset of each diagonal
     size_t elems_total = 0;         // elements incl. alignment padding
+    int perm_s = 0, perm_c = 0;     // storage order of every diagonal (perm_pos,
+                                    // storage_order.h); 0, 0 = natural
     void *dev = nullptr;            // device buffer (built handles)
 };
 
@@ -65,6 +67,9 @@ struct DiagDesc {
     int32_t m;         // d >> qb when regular
     int32_t regular;   // d is a multiple of 2^qb
     int32_t lo, hi;    // rows r with 0 <= r + d < N: [lo, hi)
+    int32_t ps, pc;    // storage order (perm_pos, storage_order.h): split bit s and chunk bits c;
+                       // 0, 0 = natural
+    int32_t plr;       // ((N - |d|) >> s) << c: entries between consecutive chunk columns
     int32_t pad;
 };
 
@@ -87,6 +92,7 @@ struct TileArgs {
                              // tile's rows at [(b * gridDim.x + tile) * 4 + 2] (others 0)
     int32_t stream_out;      // write y with non-temporal stores (see kStreamOutBytes)
     int32_t pairs;           // closed complex64 launch whose every diagonal pairs (the pair kernel)
+    int32_t perm;            // closed launch with a diagonal stored out of natural order (ps > 0)
 };
 
 // States of at least this many bytes (the chunk of up to HS_MAX_BATCH states
@@ -110,12 +116,17 @@ struct ConstructArgs {
     int32_t lb;
     int32_t nbits;
     int8_t bits[16];
+    int32_t perm_s, perm_c;  // storage order of the factor's diagonals (perm_pos)
 };
 
 // launchers (kernels.hip); all return hipError_t as int
 int launch_phase_table(int64_t N, int nz, const uint64_t *zm, const double *cf, double dt,
                        double *out, void *stream);
 int launch_construct(const ConstructArgs &a, int nd, int64_t max_len, bool c128, void *stream);
+// dst[k] = entry start + k of a diagonal of length len stored in the order
+// (s, c) (perm_pos), for k < count: the natural order of a stored range
+int launch_perm_gather(const void *src, void *dst, int64_t start, int64_t count, int64_t len, int s, int c,
+                       bool c128, void *stream);
 int launch_tile(const TileArgs &a, int batch, bool c128, bool closed, void *stream);
 // open launch with the Horner epilogue y = x0 + alpha (A x); y may alias x0, not x
 int launch_tile_horner(const TileArgs &a, int batch, bool c128, void *stream);

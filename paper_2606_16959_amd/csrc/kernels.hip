@@ -10,6 +10,7 @@
 #include <mutex>
 
 #include "hs_internal.h"
+#include "storage_order.h"
 
 namespace hs {
 
@@ -64,13 +65,15 @@ __global__ void phase_table_kernel(int64_t N, int nz, const uint64_t *__restrict
 
 // One diagonal per blockIdx.y.  Entry i of diagonal d sits at row r = i - min(d, 0),
 // column p = r + d.  Value: L[loc(r), loc(p)] (times D[p]) when r and p agree
-// outside the support, else exactly 0; computed in FP64, stored as R.
+// outside the support, else exactly 0; computed in FP64, stored as R at the
+// entry's position in the factor's storage order (perm_pos).
 template <typename R>
 __global__ void construct_kernel(ConstructArgs a) {
     const int j = blockIdx.y;
     const int64_t d = a.offs[j];
     const int64_t len = (int64_t)a.N - (d < 0 ? -d : d);
     const int64_t neg = d < 0 ? d : 0;
+    const int64_t clr = (len >> a.perm_s) << a.perm_c;
     C2<R> *out = reinterpret_cast<C2<R> *>(a.base) + a.elem_off[j];
     const uint64_t outside = ~(uint64_t)a.smask;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
@@ -101,8 +104,18 @@ __global__ void construct_kernel(ConstructArgs a) {
             vr = tr;
             vi = ti;
         }
-        out[i] = C2<R>{(R)vr, (R)vi};
+        out[perm_pos(i, a.perm_s, a.perm_c, clr)] = C2<R>{(R)vr, (R)vi};
     }
+}
+
+// dst[k] = entry start + k of a diagonal stored in the order (s, c)
+template <typename R>
+__global__ void perm_gather_kernel(const C2<R> *__restrict__ src, C2<R> *__restrict__ dst, int64_t start,
+                                   int64_t count, int64_t len, int s, int c) {
+    const int64_t clr = (len >> s) << c;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
+         k += (int64_t)gridDim.x * blockDim.x)
+        dst[k] = src[perm_pos(start + k, s, c, clr)];
 }
 
 // ------------------------------------------------------------ DIA tile kernel
@@ -246,8 +259,10 @@ constexpr int tile_pf(int B, int P, int NT) {
 }
 
 // Coefficients of one diagonal for every row pair a thread owns (masked
-// loads: invalid rows read entry 0 and are zeroed when consumed).
-template <typename R, int P, int NT, bool SINGLE = false>
+// loads: invalid rows read entry 0 and are zeroed when consumed).  PERM: the
+// diagonal may be stored out of natural order (perm_pos with its ps, pc; an
+// even entry and its successor stay adjacent, so pairs are still one load).
+template <typename R, int P, int NT, bool SINGLE = false, bool PERM = false>
 __device__ __forceinline__ void load_diag(C2<R> (&c)[P][2], const DiagDesc &dd, int tid, int T,
                                           int base, int qb, int logW) {
     const C2<R> *cp = reinterpret_cast<const C2<R> *>(dd.ptr);
@@ -262,6 +277,7 @@ __device__ __forceinline__ void load_diag(C2<R> (&c)[P][2], const DiagDesc &dd, 
             const int r0 = base + ((i0 >> logW) << qb) + (i0 & (W - 1));
             int e = r0 + neg;
             e = (e >= 0 && e < len && i0 < T) ? e : 0;   // even d: pairs never straddle lo/hi
+            if (PERM) e = perm_pos32(e, dd.ps, dd.pc, dd.plr);
             ld2(cp, e, c[p][0], c[p][1]);
         }
     } else {
@@ -273,6 +289,7 @@ __device__ __forceinline__ void load_diag(C2<R> (&c)[P][2], const DiagDesc &dd, 
             for (int k = 0; k < 2; ++k) {
                 int e = r0 + k + neg;
                 e = (e >= 0 && e < len && i0 < T) ? e : 0;
+                if (PERM) e = perm_pos32(e, dd.ps, dd.pc, dd.plr);
                 c[p][k] = ld1(cp, e);
             }
         }
@@ -284,9 +301,12 @@ __device__ __forceinline__ void load_diag(C2<R> (&c)[P][2], const DiagDesc &dd, 
 // RAG (open contiguous launches only): N need not be a multiple of the tile;
 // rows at or past N are neither loaded nor stored.
 // STREAM (not with RAG): the output is written with non-temporal stores.
+// PERM (closed launches only): some diagonals are stored out of natural
+// order (perm_pos); the others carry ps = pc = 0.
 template <typename R, int B, int RPT, bool CLOSED, bool HORNER = false, int NT = kTileThreads, bool RAG = false,
-          bool STREAM = false>
+          bool STREAM = false, bool PERM = false>
 __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
+    static_assert(!PERM || (CLOSED && !RAG && !HORNER), "out-of-order storage only in closed launches");
     static_assert(RPT % 2 == 0, "rows come in pairs");
     constexpr int P = RPT / 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -490,7 +510,7 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
         // code the one-state kernels were tuned and profiled with (the lambda
         // form schedules slightly differently).
         C2<R> c[P][2];
-        load_diag<R, P, NT, RAG>(c, a.desc[0], tid, T, base, qb, logW);
+        load_diag<R, P, NT, RAG, PERM>(c, a.desc[0], tid, T, base, qb, logW);
         __syncthreads();
         int dj = 0;
         for (int f = 0; f < a.nf; ++f) {
@@ -544,7 +564,7 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
                         }
                     }
                 }
-                if (dj + 1 < total) load_diag<R, P, NT, RAG>(c, a.desc[dj + 1], tid, T, base, qb, logW);
+                if (dj + 1 < total) load_diag<R, P, NT, RAG, PERM>(c, a.desc[dj + 1], tid, T, base, qb, logW);
             }
             if (f + 1 < a.nf) {
                 __syncthreads();
@@ -565,7 +585,7 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
         C2<R> c[PF][P][2];
 #pragma unroll
         for (int u = 0; u < PF; ++u)
-            if (u < total) load_diag<R, P, NT, RAG>(c[u], a.desc[u], tid, T, base, qb, logW);
+            if (u < total) load_diag<R, P, NT, RAG, PERM>(c[u], a.desc[u], tid, T, base, qb, logW);
         __syncthreads();
         clear_acc();
         int f = 0, fend = a.dstart[1];
@@ -582,7 +602,7 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
                     }
                     const DiagDesc dd = a.desc[dj];
                     apply(c[u], dd);
-                    if (dj + PF < total) load_diag<R, P, NT, RAG>(c[u], a.desc[dj + PF], tid, T, base, qb, logW);
+                    if (dj + PF < total) load_diag<R, P, NT, RAG, PERM>(c[u], a.desc[dj + PF], tid, T, base, qb, logW);
                 }
             }
         }
@@ -715,7 +735,7 @@ constexpr int pair_pf() {
     return pf;
 }
 
-template <int B, int RPT, int NT, bool STREAM>
+template <int B, int RPT, int NT, bool STREAM, bool PERM = false>
 __global__ __launch_bounds__(NT) void dia_pair_kernel(TileArgs a) {
     using R = float;
     static_assert(RPT % 2 == 0, "rows come in pairs");
@@ -782,7 +802,9 @@ __global__ __launch_bounds__(NT) void dia_pair_kernel(TileArgs a) {
     // are zeroed when used).  Diagonal j >= total is a placeholder of no
     // entries: every lane reads entry 0 of the last diagonal (one cached
     // line) and the values are never used; it keeps the number of loads per
-    // loop iteration fixed, so their waits stay exact.
+    // loop iteration fixed, so their waits stay exact.  PERM: the diagonal
+    // may be stored out of natural order (perm_pos keeps an even entry and its
+    // successor adjacent, and entry 0 in place).
     auto load = [&](C2<R> (&c)[P][2], int j) {
         const DiagDesc &dd = a.desc[j < total ? j : total - 1];
         const C2<R> *cp = reinterpret_cast<const C2<R> *>(dd.ptr);
@@ -793,6 +815,7 @@ __global__ __launch_bounds__(NT) void dia_pair_kernel(TileArgs a) {
             const int i0 = 2 * tid + 2 * NT * p;
             int e = row_of(i0) + neg;
             e = (e >= 0 && e < len && i0 < T) ? e : 0;
+            if (PERM) e = perm_pos32(e, dd.ps, dd.pc, dd.plr);
             ld2(cp, e, c[p][0], c[p][1]);
         }
     };
@@ -1207,6 +1230,22 @@ int launch_construct(const ConstructArgs &a, int nd, int64_t max_len, bool c128,
     return (int)hipGetLastError();
 }
 
+int launch_perm_gather(const void *src, void *dst, int64_t start, int64_t count, int64_t len, int s, int c,
+                       bool c128, void *stream) {
+    if (count <= 0) return 0;
+    if (start < 0 || start + count > len || s < c || c < 0 || s > 30) return (int)hipErrorInvalidValue;
+    const int g = grid_for(count, 256, 1 << 16);
+    if (c128)
+        hipLaunchKernelGGL(perm_gather_kernel<double>, dim3(g), dim3(256), 0, S(stream),
+                           static_cast<const C2<double> *>(src), static_cast<C2<double> *>(dst), start, count, len,
+                           s, c);
+    else
+        hipLaunchKernelGGL(perm_gather_kernel<float>, dim3(g), dim3(256), 0, S(stream),
+                           static_cast<const C2<float> *>(src), static_cast<C2<float> *>(dst), start, count, len, s,
+                           c);
+    return (int)hipGetLastError();
+}
+
 enum TileMode { kOpen = 0, kClosed = 1, kHorner = 2 };
 
 static std::mutex &lds_attr_mutex() {
@@ -1217,13 +1256,15 @@ static std::mutex &lds_attr_mutex() {
 // Launch with the smallest rows-per-thread instantiation (power of two, down
 // to one row pair) that still gives every tile row a thread: a tile smaller
 // than the kernel's capacity would otherwise issue masked loads and FMAs.
-template <typename R, int B, int RPT, bool CLOSED, bool HORNER, int NT, bool RAG = false, bool STREAM = false>
+template <typename R, int B, int RPT, bool CLOSED, bool HORNER, int NT, bool RAG = false, bool STREAM = false,
+          bool PERM = false>
 static int tile_launch(const TileArgs &a, int rows_per_thread, size_t lds, int grid, void *stream) {
     if constexpr (RPT > 2) {
         if (rows_per_thread <= RPT / 2)
-            return tile_launch<R, B, RPT / 2, CLOSED, HORNER, NT, RAG, STREAM>(a, rows_per_thread, lds, grid, stream);
+            return tile_launch<R, B, RPT / 2, CLOSED, HORNER, NT, RAG, STREAM, PERM>(a, rows_per_thread, lds, grid,
+                                                                                    stream);
     }
-    auto kern = dia_tile_kernel<R, B, RPT, CLOSED, HORNER, NT, RAG, STREAM>;
+    auto kern = dia_tile_kernel<R, B, RPT, CLOSED, HORNER, NT, RAG, STREAM, PERM>;
     if (lds > 65536) {
         // allow this instantiation the dynamic LDS the launch needs (raised
         // only when a larger launch arrives; the planner keeps lds within the
@@ -1247,14 +1288,15 @@ static int tile_launch(const TileArgs &a, int rows_per_thread, size_t lds, int g
 
 // The pair kernel with the smallest rows-per-thread instantiation that
 // gives every tile row a thread (as tile_launch).
-template <int B, int RPT, int NT, bool STREAM>
+template <int B, int RPT, int NT, bool STREAM, bool PERM = false>
 static int pair_launch(const TileArgs &a, int rows_per_thread, int grid, void *stream) {
     if constexpr (RPT > 2) {
-        if (rows_per_thread <= RPT / 2) return pair_launch<B, RPT / 2, NT, STREAM>(a, rows_per_thread, grid, stream);
+        if (rows_per_thread <= RPT / 2)
+            return pair_launch<B, RPT / 2, NT, STREAM, PERM>(a, rows_per_thread, grid, stream);
     }
     constexpr int TS = pair_lds_rows<B, RPT, NT>();
     if (a.T > TS) return (int)hipErrorInvalidValue;
-    auto kern = dia_pair_kernel<B, RPT, NT, STREAM>;
+    auto kern = dia_pair_kernel<B, RPT, NT, STREAM, PERM>;
     const size_t lds = (size_t)TS * B * sizeof(C2<float>);
     if (lds > 65536) {
         static std::atomic<int> allowed{65536};
@@ -1296,14 +1338,25 @@ static int tile_dispatch_b(const TileArgs &a, int mode, void *stream) {
     const int grid = (int)((a.N + a.T - 1) / a.T);
     const int need = (a.T + nt - 1) / nt;
     const bool st = a.stream_out != 0;         // ragged launches keep plain stores
+    // diagonals stored out of natural order are read by closed launches only
+    if (a.perm && mode != kClosed) return (int)hipErrorInvalidValue;
+    const bool pm = a.perm != 0;
     if constexpr (sizeof(R) == 4) {
-        if (mode == kClosed && a.pairs)
+        if (mode == kClosed && a.pairs) {
+            if (pm)
+                return st ? pair_launch<B, RPT, NTC, true, true>(a, need, grid, stream)
+                          : pair_launch<B, RPT, NTC, false, true>(a, need, grid, stream);
             return st ? pair_launch<B, RPT, NTC, true>(a, need, grid, stream)
                       : pair_launch<B, RPT, NTC, false>(a, need, grid, stream);
+        }
     }
-    if (mode == kClosed)
+    if (mode == kClosed) {
+        if (pm)
+            return st ? tile_launch<R, B, RPT, true, false, NTC, false, true, true>(a, need, lds, grid, stream)
+                      : tile_launch<R, B, RPT, true, false, NTC, false, false, true>(a, need, lds, grid, stream);
         return st ? tile_launch<R, B, RPT, true, false, NTC, false, true>(a, need, lds, grid, stream)
                   : tile_launch<R, B, RPT, true, false, NTC>(a, need, lds, grid, stream);
+    }
     if (mode == kOpen)
         return rag  ? tile_launch<R, B, RPT_OPEN, false, false, NTO, true>(a, need, lds, grid, stream)
                : st ? tile_launch<R, B, RPT_OPEN, false, false, NTO, false, true>(a, need, lds, grid, stream)
