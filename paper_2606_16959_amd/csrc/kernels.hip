@@ -186,6 +186,13 @@ __device__ __forceinline__ void ld2(const C2<double> *p, int i, C2<double> &a, C
 
 typedef __attribute__((address_space(1))) f4v g_f4w;
 typedef __attribute__((address_space(1))) d2v g_d2w;
+// one complex128 row of an output state (STREAM: non-temporal)
+template <bool STREAM>
+__device__ __forceinline__ void st1(C2<double> *p, int i, C2<double> a) {
+    const d2v u = {a.re, a.im};
+    if (STREAM) __builtin_nontemporal_store(u, (g_d2w *)(p) + i);
+    else *((g_d2w *)(p) + i) = u;
+}
 // rows i and i + 1 (i even) of an output state: one 16-byte store for
 // complex64, two for complex128; STREAM streams them past the caches (a
 // compile-time choice: with a run-time branch the compiler merges the two
@@ -214,6 +221,10 @@ __device__ __forceinline__ void ld2_cached(const C2<float> *p, int i, C2<float> 
     const f4v v = *((g_f4 *)(p) + (i >> 1));
     a = C2<float>{v.x, v.y};
     b = C2<float>{v.z, v.w};
+}
+__device__ __forceinline__ C2<double> ld1_cached(const C2<double> *p, int i) {
+    const d2v u = *((g_d2 *)(p) + i);
+    return C2<double>{u.x, u.y};
 }
 __device__ __forceinline__ void ld2_cached(const C2<double> *p, int i, C2<double> &a, C2<double> &b) {
     const d2v u = *((g_d2 *)(p) + i);
@@ -269,6 +280,21 @@ __device__ __forceinline__ void load_diag(C2<R> (&c)[P][2], const DiagDesc &dd, 
     const int neg = dd.off < 0 ? dd.off : 0;
     const int len = dd.hi - dd.lo;            // N - |d| entries
     const int W = 1 << logW;
+    if constexpr (sizeof(R) == 8) {
+        // complex128: the rows of pair p are (2p + k) NT + tid (tile_lidx), one
+        // 16-byte load each
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int i = (2 * p + k) * NT + tid;
+                int e = base + ((i >> logW) << qb) + (i & (W - 1)) + neg;
+                e = (e >= 0 && e < len && i < T) ? e : 0;
+                if (PERM) e = perm_pos32(e, dd.ps, dd.pc, dd.plr);
+                c[p][k] = ld1(cp, e);
+            }
+        return;
+    }
     // SINGLE: entry-wise loads (a diagonal of odd length ends inside a pair)
     if (!SINGLE && (dd.off & 1) == 0) {
 #pragma unroll
@@ -332,7 +358,13 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
 #pragma unroll
     for (int b = 0; b < B; ++b) scale[b] = inv_norm<R>(a.nrm2, b);
 
-    // local index of pair p: i0 = 2*tid + 2*NT*p (and i0 + 1)
+    // Local index of row k (0 or 1) of the thread's pair p.  complex64: two
+    // adjacent rows, i0 = 2 tid + 2 NT p and i0 + 1 (one 16-byte load or store
+    // for both); complex128: rows (2p + k) NT + tid, so that each 16-byte
+    // load, store and LDS access of a wave covers consecutive addresses
+    // (adjacent rows would give every instruction half of each cache line).
+    constexpr bool SPLIT = sizeof(R) == 8;
+    auto lidx = [&](int p, int k) { return SPLIT ? (2 * p + k) * NT + tid : 2 * tid + 2 * NT * p + k; };
     auto row_of = [&](int i) { return base + ((i >> logW) << qb) + (i & (W - 1)); };
 
     // stage the tile: issue every load, then write LDS
@@ -340,7 +372,21 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
         C2<R> u[P][2][B];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const int i0 = 2 * tid + 2 * NT * p;
+            if constexpr (SPLIT) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int i = lidx(p, k);
+                    const int r = i < T ? row_of(i) : base;
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        if (RAG) u[p][k][b] = r < a.N ? x[b * a.stride + r] : C2<R>{(R)0, (R)0};
+                        else if (CLOSED) u[p][k][b] = ld1(x + b * a.stride, r);
+                        else u[p][k][b] = ld1_cached(x + b * a.stride, r);
+                    }
+                }
+                continue;
+            }
+            const int i0 = lidx(p, 0);
             const int r0 = i0 < T ? row_of(i0) : base;
 #pragma unroll
             for (int b = 0; b < B; ++b) {
@@ -356,15 +402,14 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
             }
         }
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const int i0 = 2 * tid + 2 * NT * p;
-            if (i0 < T)
+        for (int p = 0; p < P; ++p)
 #pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    lds[b * T + i0] = cscale(u[p][0][b], scale[b]);
-                    lds[b * T + i0 + 1] = cscale(u[p][1][b], scale[b]);
-                }
-        }
+            for (int k = 0; k < 2; ++k) {
+                const int i = lidx(p, k);
+                if (i < T)
+#pragma unroll
+                    for (int b = 0; b < B; ++b) lds[b * T + i] = cscale(u[p][k][b], scale[b]);
+            }
     }
 
     // Coefficients of PF consecutive diagonals are in flight at once: after
@@ -388,13 +433,12 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
     auto apply = [&](const C2<R> (&cc)[P][2], const DiagDesc &dd) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const int i0 = 2 * tid + 2 * NT * p;
-            const int r0 = row_of(i0);
+            const int r0 = row_of(lidx(p, 0));
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                const int i = i0 + k;
-                const int r = r0 + k;
-                const bool valid = i0 < T && r >= dd.lo && r < dd.hi;
+                const int i = lidx(p, k);
+                const int r = SPLIT ? row_of(i) : r0 + k;
+                const bool valid = i < T && r >= dd.lo && r < dd.hi;
                 const C2<R> cv = cmask(cc[p][k], valid);
                 bool in;
                 int loc;
@@ -429,15 +473,14 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
     auto acc_to_lds = [&]() {
         __syncthreads();
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const int i0 = 2 * tid + 2 * NT * p;
-            if (i0 < T)
+        for (int p = 0; p < P; ++p)
 #pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    lds[b * T + i0] = acc[p][0][b];
-                    lds[b * T + i0 + 1] = acc[p][1][b];
-                }
-        }
+            for (int k = 0; k < 2; ++k) {
+                const int i = lidx(p, k);
+                if (i < T)
+#pragma unroll
+                    for (int b = 0; b < B; ++b) lds[b * T + i] = acc[p][k][b];
+            }
         __syncthreads();
     };
 
@@ -460,13 +503,12 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
 #pragma unroll
             for (int q = 0; q < G; ++q) {
                 const int p = g0 + q;
-                const int i0 = 2 * tid + 2 * NT * p;
-                const int r0 = row_of(i0);
+                const int r0 = row_of(lidx(p, 0));
 #pragma unroll
                 for (int k = 0; k < 2; ++k) {
-                    const int i = i0 + k;
-                    const int r = r0 + k;
-                    const bool valid = i0 < T && r >= dd.lo && r < dd.hi;
+                    const int i = lidx(p, k);
+                    const int r = SPLIT ? row_of(i) : r0 + k;
+                    const bool valid = i < T && r >= dd.lo && r < dd.hi;
                     const C2<R> cv = cmask(cc[p][k], valid);
                     bool in;
                     int loc;
@@ -527,13 +569,12 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
                 } else {
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        const int i0 = 2 * tid + 2 * NT * p;
-                        const int r0 = row_of(i0);
+                        const int r0 = row_of(lidx(p, 0));
 #pragma unroll
                         for (int k = 0; k < 2; ++k) {
-                            const int i = i0 + k;
-                            const int r = r0 + k;
-                            const bool valid = i0 < T && r >= dd.lo && r < dd.hi;
+                            const int i = lidx(p, k);
+                            const int r = SPLIT ? row_of(i) : r0 + k;
+                            const bool valid = i < T && r >= dd.lo && r < dd.hi;
                             const C2<R> cv = cmask(c[p][k], valid);
                             bool in;
                             int loc;
@@ -569,15 +610,14 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
             if (f + 1 < a.nf) {
                 __syncthreads();
 #pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const int i0 = 2 * tid + 2 * NT * p;
-                    if (i0 < T)
+                for (int p = 0; p < P; ++p)
 #pragma unroll
-                        for (int b = 0; b < B; ++b) {
-                            lds[b * T + i0] = acc[p][0][b];
-                            lds[b * T + i0 + 1] = acc[p][1][b];
-                        }
-                }
+                    for (int k = 0; k < 2; ++k) {
+                        const int i = lidx(p, k);
+                        if (i < T)
+#pragma unroll
+                            for (int b = 0; b < B; ++b) lds[b * T + i] = acc[p][k][b];
+                    }
                 __syncthreads();
             }
         }
@@ -616,20 +656,17 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
 #pragma unroll
         for (int b = 0; b < B; ++b) ss[b] = 0.0;
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const int i0 = 2 * tid + 2 * NT * p;
-            if (i0 < T) {
-                const int r0 = row_of(i0);
+        for (int p = 0; p < P; ++p)
 #pragma unroll
-                for (int k = 0; k < 2; ++k)
-                    if (!RAG || r0 + k < a.N)
+            for (int k = 0; k < 2; ++k) {
+                const int i = lidx(p, k);
+                if (i < T && (!RAG || row_of(i) < a.N))
 #pragma unroll
-                        for (int b = 0; b < B; ++b) {
-                            const double re = (double)acc[p][k][b].re, im = (double)acc[p][k][b].im;
-                            ss[b] += re * re + im * im;
-                        }
+                    for (int b = 0; b < B; ++b) {
+                        const double re = (double)acc[p][k][b].re, im = (double)acc[p][k][b].im;
+                        ss[b] += re * re + im * im;
+                    }
             }
-        }
         __syncthreads();
         double *red = reinterpret_cast<double *>(smem_raw);
         const int wave = tid >> 6, lane = tid & 63;
@@ -654,15 +691,19 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
         const C2<R> al{(R)a.alpha_re, (R)a.alpha_im};
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const int i0 = 2 * tid + 2 * NT * p;
+            const int i0 = lidx(p, 0), i1 = lidx(p, 1);
             const int r0 = i0 < T ? row_of(i0) : base;
+            const int r1 = SPLIT ? (i1 < T ? row_of(i1) : base) : r0 + 1;
 #pragma unroll
             for (int b = 0; b < B; ++b) {
                 C2<R> v0, v1;
                 if (RAG) {
                     const C2<R> z{(R)0, (R)0};
                     v0 = r0 < a.N ? x0[b * a.stride + r0] : z;
-                    v1 = r0 + 1 < a.N ? x0[b * a.stride + r0 + 1] : z;
+                    v1 = r1 < a.N ? x0[b * a.stride + r1] : z;
+                } else if (SPLIT) {
+                    v0 = ld1(x0 + b * a.stride, r0);
+                    v1 = ld1(x0 + b * a.stride, r1);
                 } else {
                     ld2(x0 + b * a.stride, r0, v0, v1);
                 }
@@ -675,7 +716,22 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const int i0 = 2 * tid + 2 * NT * p;
+        if constexpr (SPLIT) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int i = lidx(p, k);
+                if (i < T) {
+                    const int r = row_of(i);
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        if (!RAG) st1<STREAM>(y + b * a.stride, r, acc[p][k][b]);
+                        else if (r < a.N) y[b * a.stride + r] = acc[p][k][b];
+                    }
+                }
+            }
+            continue;
+        }
+        const int i0 = lidx(p, 0);
         if (i0 < T) {
             const int r0 = row_of(i0);
 #pragma unroll
