@@ -39,7 +39,7 @@ WORKLOAD = {
 }
 # sources that decide the tile kernel's code and launch plan
 KERNEL_SRC = [os.path.join(ROOT, "paper_2606_16959_amd", "csrc", f)
-              for f in ("kernels.hip", "hs_internal.h", "tile_plan.h", "api.hip")]
+              for f in ("kernels.hip", "hs_internal.h", "tile_plan.h", "api.hip", "storage_order.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dia_tile_tfim2d_n26.json")
 OUT_DIR = os.path.join(ROOT, "profiles")      # where summaries are written (--out-dir)
 
@@ -1176,7 +1176,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(per_launch, len(launches)),
             "kernel": "DIA tile kernel (complex64, one state, closed tiles; row form, pair form where every "
-                      "diagonal pairs)",
+                      "diagonal pairs; factors of the launch over the top qubits stored in level-major chunks)",
             "algorithmic_bytes_per_launch": [int(b) for b in per_launch],
             "avg_launch_ms": round(avg_launch_ms, 4)}
 

@@ -196,8 +196,9 @@ hs_status hs_factor_copy_diagonal(hs_factors f, int k, int j, long long start, l
  * low rows reads one short stretch per column instead of one run per level
  * 2^s entries apart.  Each diagonal still holds exactly N - |d| entries.
  * The library chooses it at build for factors applied in strided tiles whose
- * levels lie at least HAMSIM_PERM_MIN_BYTES apart; s = c = 0 is the natural
- * order.  Either output may be null. */
+ * levels lie at least HAMSIM_PERM_MIN_BYTES (default 1 MiB) apart, with
+ * runs of four of those tiles' row windows; s = c = 0 is the natural order.
+ * Either output may be null. */
 hs_status hs_factor_storage(hs_factors f, int k, int *split_bit, int *chunk_bits);
 /* Bytes of device memory an evolution of `batch` states needs: the stored
  * diagonals (Eq. 6: N - |d| entries per diagonal, each start aligned to 256

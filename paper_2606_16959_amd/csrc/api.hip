@@ -237,7 +237,10 @@ void form_runs(const Plan &P, int dtype, const PlanKey &key, EvolvePlan &ep) {
                 ep.needs_scratch = true;
             }
             run.pairs = key.pairs && dtype == HS_C64 && !run.open && !run.elementwise;
-            if (key.pairs == 1 && run.geo.qb > 0 && run.launch_batch == 1 && ((size_t)1 << run.geo.logW) * sc < 1024)
+            bool permuted = false;
+            for (int k : run.factors) permuted = permuted || P.factors[k].perm_s > 0;
+            if (key.pairs == 1 && run.geo.qb > 0 && run.launch_batch == 1 && ((size_t)1 << run.geo.logW) * sc < 1024 &&
+                !permuted)
                 run.pairs = false;
             const int64_t lowmask = (int64_t(1) << run.geo.qb) - 1;
             for (int k : run.factors)
@@ -251,37 +254,52 @@ void form_runs(const Plan &P, int dtype, const PlanKey &key, EvolvePlan &ep) {
 }
 
 // Storage order of every factor (perm_pos): a factor that the one-state plan
-// (default fusion) applies only in closed strided launches, whose level stride
-// 2^qb rows spans at least HAMSIM_PERM_MIN_BYTES (default 1 MiB, where every
-// level of a tile lands on its own 2 MB page; 0: never), is stored with
-// s = qb (the smallest over its launches) and chunks of
-// HAMSIM_PERM_CHUNK_BYTES (default 256).  Launches of other batch sizes read
-// the same storage; their tiles keep page locality while their qb is near s.
+// (default fusion) applies only in closed strided launches, whose level
+// stride 2^qb rows spans at least HAMSIM_PERM_MIN_BYTES (default 1 MiB, where
+// every level of a tile lies on its own 2 MB page; 0: never), is stored with
+// s = qb of the launch with the smallest qb.  Its chunks hold
+// HAMSIM_PERM_CHUNK_WINDOWS (default 4) of that launch's windows of W
+// consecutive rows, or HAMSIM_PERM_CHUNK_BYTES when that is set (nonzero):
+// neighbouring tiles, which run at the same time on other compute units, then
+// read each level's chunk together.  On the n = 26 TFIM step (complex64) the
+// launch whose levels lie 2 MiB apart took 3.14 ms in natural order, 2.84 ms
+// with 256-byte chunks and 2.64 ms with chunks of four windows (8 windows:
+// 2.92 ms).  Levels 32 KiB apart gained 3% the same way (2.63 -> 2.55 ms), but
+// launches of other batch sizes, which read the same storage through tiles of
+// another shape, lost up to 2% (8 states of the n = 24 MaxCut step), so the
+// default leaves them in natural order.
 void choose_storage_order(Plan &P, int dtype) {
     for (auto &f : P.factors) f.perm_s = f.perm_c = 0;
     const int min_bytes = env_int("HAMSIM_PERM_MIN_BYTES", 1 << 20, 0, 1 << 30);
     if (min_bytes == 0) return;
     const size_t sc = elem_bytes(dtype);
-    const int chunk_bytes = env_int("HAMSIM_PERM_CHUNK_BYTES", 256, 16, 1 << 20);
-    const int c = ilog2(std::max<int64_t>(2, (int64_t)chunk_bytes / (int64_t)sc));   // >= 2 entries: pairs
+    const int chunk_bytes = env_int("HAMSIM_PERM_CHUNK_BYTES", 0, 0, 1 << 24);
+    const int chunk_windows = env_int("HAMSIM_PERM_CHUNK_WINDOWS", 4, 1, 1 << 12);
     EvolvePlan ep;
     form_runs(P, dtype, plan_key(1, true), ep);
-    std::vector<int> smin(P.factors.size(), -1);
+    std::vector<int> smin(P.factors.size(), -1), wlog(P.factors.size(), 0);
     for (int part = 0; part < kParts; ++part)
         for (const Run &run : ep.runs[part]) {
             const bool strided = !run.open && !run.elementwise && run.geo.qb > 0;
             for (int k : run.factors) {
                 const int q = strided ? run.geo.qb : 0;
-                smin[k] = smin[k] < 0 ? q : std::min(smin[k], q);
+                if (smin[k] < 0 || q < smin[k]) {
+                    smin[k] = q;
+                    wlog[k] = run.geo.logW;
+                }
             }
         }
     for (size_t k = 0; k < P.factors.size(); ++k) {
         Factor &F = P.factors[k];
         const int q = smin[k];
-        if (q <= 0 || q < c || q > 30 || ((size_t)1 << q) * sc < (size_t)min_bytes) continue;
+        if (q <= 0 || q > 30 || ((size_t)1 << q) * sc < (size_t)min_bytes) continue;
         bool multiple = true;
         for (int64_t d : F.offs) multiple = multiple && ((d < 0 ? -d : d) & ((int64_t(1) << q) - 1)) == 0;
         if (!multiple) continue;
+        // chunk entries: a power of two, at least 2 (pairs stay adjacent), at most 2^q
+        const int64_t want = chunk_bytes ? (int64_t)chunk_bytes / (int64_t)sc
+                                         : ((int64_t)chunk_windows << wlog[k]);
+        const int c = std::min(q, std::max(1, ilog2(std::max<int64_t>(2, want))));
         F.perm_s = q;
         F.perm_c = c;
     }

@@ -235,10 +235,12 @@ constexpr int kReduceBlocks = 1024;   // partial sums per state (fixed: determin
 #endif
 constexpr int kTileThreads = HS_TILE_THREADS;
 
-// Closed complex128 launches of two states run twice the default threads
-// with half the rows each (same 2048-row tile): 16 waves per CU instead of
-// 8, measured 4.5% faster; for one state the same change was slower.
-constexpr bool tile_c128_pair_wide(bool c128, int batch, bool open) { return c128 && !open && batch == 2; }
+// Closed complex128 launches of two to four states run twice the default
+// threads with half the rows each (2048-row tiles): 16 waves per CU instead
+// of 8, measured 4-6% faster; for one state the same change was slower.
+constexpr bool tile_c128_pair_wide(bool c128, int batch, bool open) {
+    return c128 && !open && batch >= 2 && batch <= 4;
+}
 // Rows per thread for a launch of `batch` states: the accumulator budget
 // split over the batch rounded up to a power of two, at least one row pair.
 constexpr int tile_rpt(bool c128, int batch, bool open = false) {

@@ -33,7 +33,8 @@ def _ham(name):
     raise KeyError(name)
 
 
-def _build(hs, H, steps, dtype, order, perm, chunk=256, budget=16):
+def _build(hs, H, steps, dtype, order, perm, chunk=0, budget=16):
+    """chunk: bytes per storage chunk, 0 = the library's choice (four row windows)."""
     with env(HAMSIM_PERM_MIN_BYTES=1 if perm else 0, HAMSIM_PERM_CHUNK_BYTES=chunk):
         return hs.build_factors(H.strings, H.coeffs, H.n, 1.0, steps, budget, dtype=dtype, order=order)
 
@@ -46,17 +47,17 @@ def _states(torch, n, batch, dtype, seed):
 
 CASES = [
     # (Hamiltonian, dtype, batch, order, renorm, chunk bytes, pair-form knob)
-    ("tfim2d_4x5", "c64", 1, 1, False, 256, "1"),
+    ("tfim2d_4x5", "c64", 1, 1, False, 0, "1"),
     ("tfim2d_4x5", "c64", 1, 1, False, 256, "2"),
     ("tfim2d_4x5", "c64", 3, 2, True, 16, "1"),
     ("tfim2d_4x5", "c128", 1, 1, False, 256, "1"),
     ("tfim2d_4x5", "c128", 2, 4, False, 4096, "1"),
-    ("heisenberg_n18", "c64", 8, 1, False, 256, "1"),
+    ("heisenberg_n18", "c64", 8, 1, False, 0, "1"),
     ("heisenberg_n18", "c64", 5, 1, True, 4096, "0"),
     ("heisenberg_n18", "c128", 3, 2, False, 16, "1"),
-    ("maxcut_n20", "c64", 8, 1, False, 256, "1"),
+    ("maxcut_n20", "c64", 8, 1, False, 0, "1"),
     ("maxcut_n20", "c64", 2, 1, False, 256, "2"),
-    ("maxcut_n20", "c128", 1, 1, True, 256, "1"),
+    ("maxcut_n20", "c128", 1, 1, True, 0, "1"),
 ]
 
 
@@ -75,7 +76,9 @@ def test_permuted_storage_evolves_bit_identically(name, dtype, batch, order, ren
     esz = 16 if dtype == "c128" else 8
     for k in permuted:
         s, c = dp["factors"][k]["storage"]
-        assert c >= 1 and s >= c and (1 << c) == max(2, chunk // esz)
+        assert 1 <= c <= s
+        if chunk:
+            assert (1 << c) == min(1 << s, max(2, chunk // esz))
         assert all(abs(d) % (1 << s) == 0 for d in dp["factors"][k]["offsets"])
     psi0 = _states(torch, H.n, batch, dtype, 11)
     outs = []
@@ -92,7 +95,7 @@ def test_permuted_storage_evolves_bit_identically(name, dtype, batch, order, ren
     fp.close()
 
 
-@pytest.mark.parametrize("dtype,chunk", [("c64", 256), ("c64", 16), ("c128", 256), ("c128", 4096)])
+@pytest.mark.parametrize("dtype,chunk", [("c64", 0), ("c64", 16), ("c128", 0), ("c128", 4096)])
 def test_permuted_diagonals_copy_back_in_natural_order(dtype, chunk):
     hs, torch = hs_gpu()
     H = _ham("tfim2d_4x5")
@@ -146,9 +149,12 @@ def test_small_state_with_permuted_storage_takes_the_tile_path():
 
 def test_headline_n26_default_storage_and_bitwise_steps():
     """tfim_5x5_ancilla_n26 in complex64 with the default threshold: the
-    factors of the launch over qubits 18-24 (levels 2 MB apart) are stored
-    permuted, the others in natural order, and two steps equal the
-    natural-order build bit for bit."""
+    factors of the strided launch over qubits 18-24 (levels 2 MiB apart,
+    windows of 64 rows) are stored permuted with chunks of four windows, the
+    other launches' factors (contiguous; levels 32 KiB apart) in natural
+    order, and two steps equal the natural-order build bit for bit.  With
+    the threshold at 32 KiB the middle launch's factors are permuted too
+    (windows of 128 rows)."""
     hs, torch = hs_gpu()
     from workloads import workload_hamiltonian
     H = workload_hamiltonian("tfim_5x5_ancilla_n26")
@@ -158,13 +164,11 @@ def test_headline_n26_default_storage_and_bitwise_steps():
     launches = fp.step_launches(1)
     seq = fp.part_sequence(0, dp)
     perm = {k for k, f in enumerate(dp["factors"]) if f["storage"][0] > 0}
-    # three launches: qubits 0-12 (contiguous), 12-17 (levels 32 KiB apart),
-    # 18-24 (levels 2 MiB apart): only the last launch's factors are permuted
     assert len(launches) == 3
-    first, nf = launches[2]
-    assert perm == set(seq[first:first + nf])
-    for k in perm:
-        assert dp["factors"][k]["storage"] == (18, 5)
+    (f0, n0), (f1, n1), (f2, n2) = launches
+    assert perm == set(seq[f2:f2 + n2])
+    for k in seq[f2:f2 + n2]:
+        assert dp["factors"][k]["storage"] == (18, 8)
     psi0 = _states(torch, 26, 1, "c64", 3)
     pa = psi0.clone()
     hs.evolve(fp, pa, 2)
@@ -172,6 +176,19 @@ def test_headline_n26_default_storage_and_bitwise_steps():
     a = pa.cpu().numpy()
     del pa
     fp.close()
+    with env(HAMSIM_PERM_MIN_BYTES=32 << 10):
+        fm = hs.build_factors(H.strings, H.coeffs, 26, 1.0, 50, 16, dtype="c64")
+    dm = fm.describe()
+    for k in seq[f1:f1 + n1]:
+        assert dm["factors"][k]["storage"] == (12, 9)
+    for k in seq[f2:f2 + n2]:
+        assert dm["factors"][k]["storage"] == (18, 8)
+    pm = psi0.clone()
+    hs.evolve(fm, pm, 2)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.view(np.uint8), pm.cpu().numpy().view(np.uint8))
+    del pm
+    fm.close()
     with env(HAMSIM_PERM_MIN_BYTES=0):
         fn = hs.build_factors(H.strings, H.coeffs, 26, 1.0, 50, 16, dtype="c64")
     assert all(f["storage"] == (0, 0) for f in fn.describe()["factors"])
