@@ -205,11 +205,16 @@ def serve_leg(torch, n_jobs, rate, slots, oracle_nmax, jsonl_dir=None):
     return st
 
 
-def summarize_profiles(trace_dir, fetch_dir, write_dir, command, extra_dirs=()):
+def summarize_profiles(trace_dir, fetch_dir, write_dir, command, extra_dirs=(), bench_trace=None, bench_log=None):
     """Turn rocprofv3 CSV output of bench.py runs into the committed summaries:
     per-kernel durations (trace) and per-launch HBM bytes of the DIA tile
     kernel from FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each scaled by
-    what the same counter reads for the 2 GiB device copies the run makes."""
+    what the same counter reads for the 2 GiB device copies the run makes.
+    bench_trace: a kernel trace of the default bench run itself, whose first
+    tile dispatches are the headline's warm-up and timed steps; their
+    durations are set beside the bench line of that run (bench_log), since
+    where the 65 GB of diagonals land in HBM moves the step time by a few
+    percent from one process to the next."""
     import csv
     import glob
 
@@ -290,6 +295,31 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, command, extra_dirs=()):
                "on 128-byte requests it reads half the bytes: the copy calibration's factor 2."]
     md += ["", f"Average over the {nl} launches of a step: "
            f"{float(np.mean([sum(x) / max(1, len(x)) for x in durs])):.4f} ms per launch."]
+    if bench_trace:
+        line = None
+        if bench_log:
+            with open(bench_log) as fh:
+                for ln in fh:
+                    if ln.startswith('{"metric"'):
+                        line = json.loads(ln)
+        warm, steps = (line["warmup"], line["steps"]) if line else (3, 20)
+        bt = sorted((r for r in rows(bench_trace, "*kernel_trace.csv") if _step_kernel(r["Kernel_Name"])),
+                    key=lambda r: int(r["Start_Timestamp"]))[warm * nl:(warm + steps) * nl]
+        bd = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in bt]
+        pos = [float(np.mean(bd[j::nl])) for j in range(nl)]
+        md += ["", "## The bench run itself", "",
+               f"Kernel trace of the default `python3 bench.py` run (rocprofv3 --kernel-trace), its {steps} timed "
+               f"headline steps after {warm} warm-up steps: the first {(warm + steps) * nl} tile dispatches of the "
+               "process.", "", "| launch | kernel form | avg ms | algorithmic GB | GB/s |", "|---|---|---|---|---|"]
+        alg = line["roofline"]["algorithmic_bytes_per_launch"] if line else [None] * nl
+        for j in range(nl):
+            gbs = f"{alg[j] / (pos[j] * 1e-3) / 1e9:.0f}" if alg[j] else "-"
+            gb = f"{alg[j] / 1e9:.3f}" if alg[j] else "-"
+            md.append(f"| {j} | {forms[j]} | {pos[j]:.3f} | {gb} | {gbs} |")
+        md += ["", f"Average launch: {float(np.mean(bd)):.4f} ms in the trace"
+               + (f"; the same run's bench line (HIP events on the launch stream): {line['roofline']['avg_launch_ms']} "
+                  f"ms per launch, {line['ms_per_step']} ms per step, {line['value']} GB/s = "
+                  f"{line['roofline']['frac']:.4f} of 8 TB/s." if line else ".")]
     with open(os.path.join(OUT_DIR, "dia_tile_tfim2d_n26.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
     with open(os.path.join(OUT_DIR, os.path.basename(TRAFFIC_FILE)), "w") as fh:
@@ -1068,6 +1098,8 @@ def main():
     ap.add_argument("--summarize-profiles", nargs="+", metavar="DIR",
                     help="TRACE FETCH WRITE [REQUEST_COUNTER_DIR...]: write profiles/ summaries from rocprofv3 output")
     ap.add_argument("--profile-command", default="")
+    ap.add_argument("--bench-trace", default=None, help="kernel trace of the default bench run (--summarize-profiles)")
+    ap.add_argument("--bench-log", default=None, help="stdout of that run (its bench line)")
     ap.add_argument("--summarize-taylor-profiles", nargs=4, metavar=("TRACE", "FETCH", "WRITE", "LEG_OUTPUT"),
                     help="write the fused Taylor update's profile summary from rocprofv3 output directories")
     ap.add_argument("--sweep", action="store_true", help="launch-plan variants (writes profiles/)")
@@ -1079,7 +1111,7 @@ def main():
         os.makedirs(OUT_DIR, exist_ok=True)
     if args.summarize_profiles:
         tr, fe, wr, *extra = args.summarize_profiles
-        summarize_profiles(tr, fe, wr, args.profile_command, extra)
+        summarize_profiles(tr, fe, wr, args.profile_command, extra, args.bench_trace, args.bench_log)
         return
     if args.summarize_taylor_profiles:
         summarize_taylor_profiles(*args.summarize_taylor_profiles)
