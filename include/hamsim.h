@@ -137,8 +137,10 @@ hs_status hs_build_factors(int n_qubits, int n_terms, const char *const *pauli_t
  * contiguous eighths of their tiles to the 8 XCDs: 0 none, 1 all, 2 strided,
  * 3 contiguous, default 3) and HAMSIM_PAIR_LDS (which closed complex64
  * launches whose row pairs read adjacent LDS partners use the pair kernel:
- * 0 none, 1 all but one-state strided launches with row runs under 1 KiB,
- * 2 all; default 1).  Results are the same bits for every setting.
+ * 0 none, 1 all but one-state strided launches with row runs under 1 KiB
+ * whose factors are stored in natural order, 2 all; default 1).  Results are
+ * the same bits for every setting, and for every storage order
+ * (hs_factor_storage).
  * A factor whose coupling range fits no tile held in LDS (e.g. X_0 X_{n-1}
  * at large n) is applied out of place into a scratch state (allocated on
  * first use, counted by hs_footprint) and copied back.  Calls that share a
