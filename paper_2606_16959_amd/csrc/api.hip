@@ -830,12 +830,22 @@ hs_status hs_factor_copy_diagonal(hs_factors f, int k, int j, long long start, l
         HS_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
         return HS_OK;
     }
-    // stored out of natural order: gather the range into a temporary first
+    // stored out of natural order: gather the range in pieces of at most
+    // 2^22 entries into a temporary, copying each piece to the host
+    const long long piece = std::min<long long>(count, 1ll << 22);
     void *tmp = nullptr;
-    HS_HIP(hipMallocAsync(&tmp, (size_t)count * sc, st), "hipMallocAsync(diagonal copy)");
-    int e = hs::launch_perm_gather(src, tmp, start, count, len, F->perm_s, F->perm_c, f->dtype == HS_C128, stream);
-    hipError_t he = e ? (hipError_t)e
-                      : hipMemcpyAsync(host_dst, tmp, (size_t)count * sc, hipMemcpyDeviceToHost, st);
+    HS_HIP(hipMallocAsync(&tmp, (size_t)piece * sc, st), "hipMallocAsync(diagonal copy)");
+    hipError_t he = hipSuccess;
+    for (long long k0 = 0; k0 < count && he == hipSuccess; k0 += piece) {
+        const long long m = std::min(piece, count - k0);
+        const int e = hs::launch_perm_gather(src, tmp, start + k0, m, len, F->perm_s, F->perm_c,
+                                             f->dtype == HS_C128, stream);
+        he = e ? (hipError_t)e
+               : hipMemcpyAsync(static_cast<char *>(host_dst) + (size_t)k0 * sc, tmp, (size_t)m * sc,
+                                hipMemcpyDeviceToHost, st);
+        // the next piece reuses the temporary: wait for this copy first
+        if (he == hipSuccess) he = hipStreamSynchronize(st);
+    }
     const hipError_t fe = hipFreeAsync(tmp, st);
     const hipError_t se = hipStreamSynchronize(st);
     if (he != hipSuccess) return hip_fail(he, "diagonal gather");

@@ -175,6 +175,10 @@ def test_headline_n26_default_storage_and_bitwise_steps():
     torch.cuda.synchronize()
     a = pa.cpu().numpy()
     del pa
+    # a whole permuted diagonal (about 2^26 entries: the copy gathers it in pieces)
+    kd = seq[f2]
+    dd = dp["factors"][kd]["offsets"][0]
+    diag_p = fp.copy_diagonal(kd, 0, dd)
     fp.close()
     with env(HAMSIM_PERM_MIN_BYTES=32 << 10):
         fm = hs.build_factors(H.strings, H.coeffs, 26, 1.0, 50, 16, dtype="c64")
@@ -192,6 +196,10 @@ def test_headline_n26_default_storage_and_bitwise_steps():
     with env(HAMSIM_PERM_MIN_BYTES=0):
         fn = hs.build_factors(H.strings, H.coeffs, 26, 1.0, 50, 16, dtype="c64")
     assert all(f["storage"] == (0, 0) for f in fn.describe()["factors"])
+    diag_n = fn.copy_diagonal(kd, 0, dd)
+    assert diag_n.shape == ((1 << 26) - abs(dd),)
+    assert np.array_equal(diag_p.view(np.uint8), diag_n.view(np.uint8))
+    del diag_p, diag_n
     pb = psi0.clone()
     hs.evolve(fn, pb, 2)
     torch.cuda.synchronize()
