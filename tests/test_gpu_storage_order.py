@@ -90,6 +90,15 @@ def test_permuted_storage_evolves_bit_identically(name, dtype, batch, order, ren
             torch.cuda.synchronize()
         outs.append(p.cpu().numpy())
     assert np.array_equal(outs[0].view(np.uint8), outs[1].view(np.uint8))
+    # one launch per factor: a factor runs alone, in the tile its own flips
+    # need (contiguous when they fit one), whatever order it is stored in
+    unfused = []
+    for f in (fn, fp):
+        p = psi0.clone()
+        hs.evolve(f, p, 3, renorm=renorm, fuse=False)
+        torch.cuda.synchronize()
+        unfused.append(p.cpu().numpy())
+    assert np.array_equal(unfused[0].view(np.uint8), unfused[1].view(np.uint8))
     assert fp.check_closure() and fn.check_closure()
     fn.close()
     fp.close()
