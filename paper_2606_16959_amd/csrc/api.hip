@@ -98,8 +98,10 @@ struct Run {
     bool open = false;          // no closed tile holds the factor's coupling range: open
                                 // launch into the scratch state, then copied back
     bool pairs = false;         // closed complex64 launch whose every diagonal pairs: the
-                                // partners of a thread's two rows are adjacent, even-aligned
-                                // LDS entries (regular offset, and W even or the offset even)
+                                // partners of a thread's two rows are adjacent LDS entries
+                                // (regular offset; even-aligned unless the offset is odd)
+    bool pairs_odd = false;     // ... and some offset is odd (contiguous tile, one-row windows):
+                                // the pair kernel's odd-offset path
     bool perm = false;          // some diagonal is stored out of natural order (perm_pos)
     int desc_start = 0;
     std::vector<int> dstart;    // per factor, relative to desc_start (size nf + 1)
@@ -243,9 +245,22 @@ void form_runs(const Plan &P, int dtype, const PlanKey &key, EvolvePlan &ep) {
                 !permuted)
                 run.pairs = false;
             const int64_t lowmask = (int64_t(1) << run.geo.qb) - 1;
+            // odd offsets pair in contiguous tiles; by default only in launches
+            // of up to 4 states (at 8 the clamped reads cost more than the
+            // row kernel's bank conflicts)
+            const bool odd_ok = (key.pairs == 2 || (key.pairs == 1 && run.launch_batch <= 4)) &&
+                                run.geo.qb == 0 && run.geo.logW == 0 && !permuted;
             for (int k : run.factors)
-                for (int64_t d : P.factors[k].offs)
-                    if ((d & lowmask) != 0 || (run.geo.logW == 0 && (d & 1))) run.pairs = false;
+                for (int64_t d : P.factors[k].offs) {
+                    if ((d & lowmask) != 0) run.pairs = false;
+                    if (run.geo.logW == 0 && (d & 1)) {
+                        if (odd_ok && P.N - (d < 0 ? -d : d) >= 2)
+                            run.pairs_odd = true;
+                        else
+                            run.pairs = false;
+                    }
+                }
+            if (!run.pairs) run.pairs_odd = false;
             runs.push_back(run);
             f = g;
         }
@@ -394,7 +409,7 @@ hs_status launch_run(hs_factors_s *h, const EvolvePlan &ep, const Run &run, void
         a.viol = run.open ? nullptr : h->viol_dev;
         a.swizzle = swizzled(ep.swizzle, run.geo) ? 1 : 0;
         a.stream_out = stream_out(chunk, P.N, h->dtype);
-        a.pairs = run.pairs ? 1 : 0;
+        a.pairs = run.pairs ? (run.pairs_odd ? 2 : 1) : 0;
         a.perm = run.perm ? 1 : 0;
         // partials of state b0 + b at [((b0 + b) * tiles + tile) * 4]
         a.norm_out = norm_partials ? norm_partials + (size_t)b0 * (P.N / run.geo.T) * 4 : nullptr;

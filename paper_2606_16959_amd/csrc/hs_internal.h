@@ -91,7 +91,8 @@ struct TileArgs {
     double *norm_out;        // or null: per tile and state, the FP64 sum of |y|^2 over the
                              // tile's rows at [(b * gridDim.x + tile) * 4 + 2] (others 0)
     int32_t stream_out;      // write y with non-temporal stores (see kStreamOutBytes)
-    int32_t pairs;           // closed complex64 launch whose every diagonal pairs (the pair kernel)
+    int32_t pairs;           // closed complex64 launch in the pair kernel: 1 even offsets only,
+                             // 2 some odd offsets (contiguous tiles)
     int32_t perm;            // closed launch with a diagonal stored out of natural order (ps > 0)
 };
 

@@ -183,6 +183,14 @@ __device__ __forceinline__ void ld2(const C2<double> *p, int i, C2<double> &a, C
     a = ld1(p, i);
     b = ld1(p, i + 1);
 }
+// entries i and i + 1 for any i (8-byte aligned 16-byte load)
+typedef float f4u __attribute__((ext_vector_type(4))) __attribute__((aligned(8)));
+typedef const __attribute__((address_space(1))) f4u g_f4u;
+__device__ __forceinline__ void ld2u(const C2<float> *p, int i, C2<float> &a, C2<float> &b) {
+    const f4u v = HS_LOAD((g_f4u *)(p + i));
+    a = C2<float>{v.x, v.y};
+    b = C2<float>{v.z, v.w};
+}
 
 typedef __attribute__((address_space(1))) f4v g_f4w;
 typedef __attribute__((address_space(1))) d2v g_d2w;
@@ -791,10 +799,11 @@ constexpr int pair_pf() {
     return pf;
 }
 
-template <int B, int RPT, int NT, bool STREAM, bool PERM = false>
+template <int B, int RPT, int NT, bool STREAM, bool PERM = false, bool ODD = false>
 __global__ __launch_bounds__(NT) void dia_pair_kernel(TileArgs a) {
     using R = float;
     static_assert(RPT % 2 == 0, "rows come in pairs");
+    static_assert(!(PERM && ODD), "odd offsets occur in contiguous tiles, which keep natural order");
     constexpr int P = RPT / 2;
     constexpr int TS = pair_lds_rows<B, RPT, NT>();       // LDS rows per state (>= T)
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -841,7 +850,10 @@ __global__ __launch_bounds__(NT) void dia_pair_kernel(TileArgs a) {
     // 16-byte pair loads per thread, so that a workgroup of few row pairs per
     // thread (large batches: one workgroup per CU) still keeps the CU's share
     // of HBM busy while it computes.
-    constexpr int PF = pair_pf<B, P, NT>();
+    // (the odd-offset path's clamped loads and selects take registers of
+    // the ring: at most 4 diagonals, one fewer than otherwise)
+    constexpr int PF0 = pair_pf<B, P, NT>();
+    constexpr int PF = !ODD ? PF0 : (PF0 - 1 < 1 ? 1 : (PF0 - 1 > 4 ? 4 : PF0 - 1));
     const int total = a.dstart[a.nf];
     C2<R> acc[P][2][B];
     bool viol = false;
@@ -866,6 +878,25 @@ __global__ __launch_bounds__(NT) void dia_pair_kernel(TileArgs a) {
         const C2<R> *cp = reinterpret_cast<const C2<R> *>(dd.ptr);
         const int neg = dd.off < 0 ? dd.off : 0;
         const int len = j < total ? dd.hi - dd.lo : 0;
+        if (ODD && (dd.off & 1)) {
+            // odd offset (contiguous tile, one-row windows): the pair's
+            // entries e, e + 1 start at any entry.  The load stays inside
+            // the diagonal's N - |d| >= 2 entries; a pair with one row out
+            // of range takes its in-range entry from the clamped load (the
+            // other is zeroed when used).
+            const int lim = dd.hi - dd.lo;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int i0 = 2 * tid + 2 * NT * p;
+                const int e = row_of(i0) + neg;
+                const int el = min(max(e, 0), lim - 2);
+                C2<R> v0, v1;
+                ld2u(cp, el, v0, v1);
+                c[p][0] = e == el ? v0 : v1;
+                c[p][1] = e + 1 == el ? v0 : v1;
+            }
+            return;
+        }
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const int i0 = 2 * tid + 2 * NT * p;
@@ -877,6 +908,41 @@ __global__ __launch_bounds__(NT) void dia_pair_kernel(TileArgs a) {
     };
     auto apply = [&](const C2<R> (&cc)[P][2], const DiagDesc &dd) {
         const int mW = dd.m * W;
+        if (ODD && (dd.off & 1)) {
+            // odd offset: rows i0, i0 + 1 meet partners s, s + 1 (s = i0 + m,
+            // odd); each row has its own range and closure test.  The LDS
+            // read of the partner pair is clamped into the tile; in a wave
+            // whose pairs all lie inside it, no selects are needed.
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int i0 = 2 * tid + 2 * NT * p;
+                const int r0 = row_of(i0);
+                const bool v0 = i0 < T && r0 >= dd.lo && r0 < dd.hi;
+                const bool v1 = i0 < T && r0 + 1 >= dd.lo && r0 + 1 < dd.hi;
+                const C2<R> c0 = cmask(cc[p][0], v0), c1 = cmask(cc[p][1], v1);
+                const int sp = i0 + mW;
+                const bool in0 = (unsigned)sp < (unsigned)T, in1 = (unsigned)(sp + 1) < (unsigned)T;
+                viol = viol || (!in0 && (c0.re != (R)0 || c0.im != (R)0)) ||
+                       (!in1 && (c1.re != (R)0 || c1.im != (R)0));
+                const int sl = min(max(sp, 0), T - 2);
+                const bool exact = sp == sl, low = sp + 1 == sl;
+                if (__all(exact)) {
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        cfma(acc[p][0][b], c0, lds[b * TS + sl]);
+                        cfma(acc[p][1][b], c1, lds[b * TS + sl + 1]);
+                    }
+                } else {
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        const C2<R> lo = lds[b * TS + sl], hi = lds[b * TS + sl + 1];
+                        cfma(acc[p][0][b], c0, exact ? lo : hi);
+                        cfma(acc[p][1][b], c1, low ? lo : hi);
+                    }
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const int i0 = 2 * tid + 2 * NT * p;
@@ -1344,15 +1410,17 @@ static int tile_launch(const TileArgs &a, int rows_per_thread, size_t lds, int g
 
 // The pair kernel with the smallest rows-per-thread instantiation that
 // gives every tile row a thread (as tile_launch).
-template <int B, int RPT, int NT, bool STREAM, bool PERM = false>
+template <int B, int RPT, int NT, bool STREAM, bool PERM = false, bool ODD = false>
 static int pair_launch(const TileArgs &a, int rows_per_thread, int grid, void *stream) {
     if constexpr (RPT > 2) {
         if (rows_per_thread <= RPT / 2)
-            return pair_launch<B, RPT / 2, NT, STREAM, PERM>(a, rows_per_thread, grid, stream);
+            return pair_launch<B, RPT / 2, NT, STREAM, PERM, ODD>(a, rows_per_thread, grid, stream);
     }
     constexpr int TS = pair_lds_rows<B, RPT, NT>();
     if (a.T > TS) return (int)hipErrorInvalidValue;
-    auto kern = dia_pair_kernel<B, RPT, NT, STREAM, PERM>;
+    // odd offsets: contiguous tiles of one-row windows only
+    if (ODD && (a.qb != 0 || a.logW != 0 || a.T != (1 << a.kb))) return (int)hipErrorInvalidValue;
+    auto kern = dia_pair_kernel<B, RPT, NT, STREAM, PERM, ODD>;
     const size_t lds = (size_t)TS * B * sizeof(C2<float>);
     if (lds > 65536) {
         static std::atomic<int> allowed{65536};
@@ -1398,6 +1466,11 @@ static int tile_dispatch_b(const TileArgs &a, int mode, void *stream) {
     if (a.perm && mode != kClosed) return (int)hipErrorInvalidValue;
     const bool pm = a.perm != 0;
     if constexpr (sizeof(R) == 4) {
+        if (mode == kClosed && a.pairs == 2) {      // some diagonals have odd offsets
+            if (pm) return (int)hipErrorInvalidValue;
+            return st ? pair_launch<B, RPT, NTC, true, false, true>(a, need, grid, stream)
+                      : pair_launch<B, RPT, NTC, false, false, true>(a, need, grid, stream);
+        }
         if (mode == kClosed && a.pairs) {
             if (pm)
                 return st ? pair_launch<B, RPT, NTC, true, true>(a, need, grid, stream)
