@@ -1207,8 +1207,9 @@ def main():
     achieved = avg_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(per_launch, len(launches)),
-            "kernel": "DIA tile kernel (complex64, one state, closed tiles; row form, pair form where every "
-                      "diagonal pairs; factors of the launch over the top qubits stored in level-major chunks)",
+            "kernel": "DIA tile kernel (complex64, one state, closed tiles, all three launches in the pair form, "
+                      "odd offsets of the contiguous tile included; factors of the launch over the top qubits "
+                      "stored in level-major chunks)",
             "algorithmic_bytes_per_launch": [int(b) for b in per_launch],
             "avg_launch_ms": round(avg_launch_ms, 4)}
 
