@@ -234,6 +234,15 @@ constexpr int kReduceBlocks = 1024;   // partial sums per state (fixed: determin
 #define HS_TILE_LDS_BYTES 131072 // largest staged tile (all states); the planner also
                                  // respects the device's per-workgroup LDS limit
 #endif
+#ifndef HS_TILE_LDS_MAX_BYTES
+#define HS_TILE_LDS_MAX_BYTES 163840 // a CU's whole LDS: closed complex64 launches of 5
+                                     // states stage 4096-row tiles in it
+#endif
+// LDS budget of a tile: the general one, or the whole LDS for the one shape
+// that needs it to double its tile (5 complex64 states, closed)
+constexpr int tile_lds_bytes(bool c128, int batch, bool open) {
+    return (!c128 && !open && batch == 5) ? HS_TILE_LDS_MAX_BYTES : HS_TILE_LDS_BYTES;
+}
 constexpr int kTileThreads = HS_TILE_THREADS;
 
 // Closed complex128 launches of two to four states run twice the default
@@ -249,6 +258,7 @@ constexpr int tile_rpt(bool c128, int batch, bool open = false) {
     while (bp < batch) bp <<= 1;
     if (tile_c128_pair_wide(c128, batch, open)) bp *= 2;
     const int acc = c128 ? HS_TILE_ACC_C128 : (open ? HS_TILE_ACC_C64_OPEN : HS_TILE_ACC_C64);
+    if (tile_lds_bytes(c128, batch, open) > HS_TILE_LDS_BYTES) return 4;   // 4096-row tiles
     return acc / bp >= 2 ? acc / bp : 2;
 }
 // Threads per workgroup: closed complex64 launches of 3-8 states use twice
@@ -261,9 +271,10 @@ constexpr int tile_threads(bool c128, int batch, bool open = false) {
                                                                                     : kTileThreads;
 }
 // Rows of the largest tile: all threads' rows, capped by an LDS budget.
-constexpr int tile_rows_cap(bool c128, int batch, bool open = false, int lds_bytes = HS_TILE_LDS_BYTES) {
+constexpr int tile_rows_cap(bool c128, int batch, bool open = false, int lds_bytes = HS_TILE_LDS_MAX_BYTES) {
     const int rows = tile_threads(c128, batch, open) * tile_rpt(c128, batch, open);
-    const int lds_rows = lds_bytes / (batch * (c128 ? 16 : 8));
+    const int budget = lds_bytes < tile_lds_bytes(c128, batch, open) ? lds_bytes : tile_lds_bytes(c128, batch, open);
+    const int lds_rows = budget / (batch * (c128 ? 16 : 8));
     int cap = 1;
     while (cap * 2 <= rows && cap * 2 <= lds_rows) cap *= 2;
     return cap;

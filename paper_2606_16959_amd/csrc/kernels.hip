@@ -779,7 +779,7 @@ __global__ __launch_bounds__(NT) void dia_tile_kernel(TileArgs a) {
 template <int B, int RPT, int NT>
 constexpr int pair_lds_rows() {
     int rows = NT * RPT;
-    while (rows > 2 && (long)rows * B * 8 > HS_TILE_LDS_BYTES) rows >>= 1;
+    while (rows > 2 && (long)rows * B * 8 > tile_lds_bytes(false, B, false)) rows >>= 1;
     return rows;
 }
 
@@ -1452,7 +1452,7 @@ static int tile_dispatch_b(const TileArgs &a, int mode, void *stream) {
     // budget; only open contiguous launches may end in a partial tile
     const int nt = mode == kClosed ? NTC : NTO;
     const int rpt = mode == kClosed ? RPT : RPT_OPEN;
-    if (a.T < 2 || a.T > nt * rpt || lds > (size_t)HS_TILE_LDS_BYTES) return (int)hipErrorInvalidValue;
+    if (a.T < 2 || a.T > nt * rpt || lds > (size_t)tile_lds_bytes(c128, B, mode != kClosed)) return (int)hipErrorInvalidValue;
     // a thread's row pair must be adjacent state rows: strided tiles need W >= 2
     if (a.qb != 0 && a.logW < 1) return (int)hipErrorInvalidValue;
     const bool rag = a.ragged != 0;

@@ -36,7 +36,7 @@ inline int lds_budget() {
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lim <= 0)
             lim = 65536;
-        return std::min(lim, (int)HS_TILE_LDS_BYTES);
+        return std::min(lim, (int)HS_TILE_LDS_MAX_BYTES);
     }();
     return v;
 }

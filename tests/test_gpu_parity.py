@@ -179,6 +179,35 @@ def test_evolve_tfim_5x5_n26_full_size_few_steps():
     assert np.abs(got - ref).max() <= bound
 
 
+def test_five_states_on_whole_lds_tiles_match_single_state_runs():
+    """Closed complex64 launches of 5 states stage 4096-row tiles in the
+    whole 160 KiB LDS of a CU: a maxcut_3reg_n24 step takes 3 launches, as
+    with 4 states (2048-row tiles would need 4), and each column equals its
+    one-state run bit for bit (with per-step renormalisation the FP64 norm
+    sums over other tiles, so the columns agree to FP32 rounding)."""
+    hs, torch = hs_gpu()
+    note("evolve maxcut_3reg_n24 B=5 c64 (4096-row tiles), 2 steps, columns vs one-state runs")
+    H = workload_hamiltonian("maxcut_3reg_n24")
+    psi0 = ws.workload_states("maxcut_3reg_n24", np.complex64)[:5]
+    f = hs.build_factors(H.strings, H.coeffs, 24, 1.0, 200, 16, dtype="c64")
+    assert len(f.step_launches(5)) == 3 and len(f.step_launches(4)) == 3 and len(f.step_launches(6)) == 4
+    for renorm in (False, True):
+        five = _to_dev(torch, psi0, np.complex64)
+        hs.evolve(f, five, 2, renorm=renorm)
+        got = five.cpu().numpy()
+        del five
+        for b in (0, 2, 4):
+            one = _to_dev(torch, psi0[b:b + 1], np.complex64)
+            hs.evolve(f, one, 2, renorm=renorm)
+            alone = one.cpu().numpy()[0]
+            if renorm:
+                assert np.max(np.abs(alone - got[b])) < 1e-9, b
+            else:
+                assert np.array_equal(alone.view(np.uint8), got[b].view(np.uint8)), b
+    assert f.check_closure()
+    f.close()
+
+
 def test_evolve_maxcut_n24_full_size_batched():
     hs, torch = hs_gpu()
     note("evolve maxcut_3reg_n24 B=8 c64, 2 of 200 steps, vs oracle + column invariance")
