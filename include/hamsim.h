@@ -129,7 +129,9 @@ hs_status hs_build_factors(int n_qubits, int n_terms, const char *const *pauli_t
  * flags: HS_RENORM (FP64 norm after each step, applied as a scale when the
  * next step loads the state, and once more at the end), HS_NO_FUSE.
  * complex64 states accumulate in FP32 over ascending offsets; complex128 in
- * FP64.  Results do not depend on the batch size or on fusion.
+ * FP64.  Results do not depend on the batch size or on fusion (with
+ * HS_RENORM the FP64 norm sums per tile, and tiles differ between batch
+ * sizes, so renormalised complex128 results agree to FP64 rounding).
  * Launch shapes follow four environment variables, read at every call (a
  * handle keeps one launch plan per setting): HAMSIM_WMIN_BYTES (shortest
  * row run of a strided tile, default 256), HAMSIM_MAX_FUSE (factors per

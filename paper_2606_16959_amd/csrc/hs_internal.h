@@ -259,6 +259,8 @@ constexpr int tile_rpt(bool c128, int batch, bool open = false) {
     if (tile_c128_pair_wide(c128, batch, open)) bp *= 2;
     const int acc = c128 ? HS_TILE_ACC_C128 : (open ? HS_TILE_ACC_C64_OPEN : HS_TILE_ACC_C64);
     if (tile_lds_bytes(c128, batch, open) > HS_TILE_LDS_BYTES) return 4;   // 4096-row tiles
+    if (c128 && !open && batch == 2) return 4;   // 4096-row tiles (128 KiB): 3 launches for
+                                                 // a 24-qubit MaxCut step instead of 4
     return acc / bp >= 2 ? acc / bp : 2;
 }
 // Threads per workgroup: closed complex64 launches of 3-8 states use twice

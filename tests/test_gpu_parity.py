@@ -208,6 +208,27 @@ def test_five_states_on_whole_lds_tiles_match_single_state_runs():
     f.close()
 
 
+def test_two_complex128_states_on_4096_row_tiles_match_single_state_runs():
+    """Closed complex128 launches of 2 states stage 4096-row tiles (128 KiB,
+    as one state): heisenberg_chain_n20 keeps the one-state launch count and
+    each column equals its one-state run bit for bit."""
+    hs, torch = hs_gpu()
+    note("evolve heisenberg_chain_n20 B=2 c128 (4096-row tiles), 3 steps, columns vs one-state runs")
+    H = workload_hamiltonian("heisenberg_chain_n20")
+    psi0 = np.stack([ws.random_phase_state(20, 70 + b, np.complex128) for b in range(2)])
+    f = hs.build_factors(H.strings, H.coeffs, 20, 2.0, 100, 16, dtype="c128")
+    assert len(f.step_launches(2)) == len(f.step_launches(1))
+    two = _to_dev(torch, psi0, np.complex128)
+    hs.evolve(f, two, 3)
+    got = two.cpu().numpy()
+    for b in range(2):
+        one = _to_dev(torch, psi0[b:b + 1], np.complex128)
+        hs.evolve(f, one, 3)
+        assert np.array_equal(one.cpu().numpy()[0].view(np.uint8), got[b].view(np.uint8)), b
+    assert f.check_closure()
+    f.close()
+
+
 def test_evolve_maxcut_n24_full_size_batched():
     hs, torch = hs_gpu()
     note("evolve maxcut_3reg_n24 B=8 c64, 2 of 200 steps, vs oracle + column invariance")
