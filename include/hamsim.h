@@ -139,8 +139,8 @@ hs_status hs_build_factors(int n_qubits, int n_terms, const char *const *pauli_t
  * contiguous eighths of their tiles to the 8 XCDs: 0 none, 1 all, 2 strided,
  * 3 contiguous, default 3) and HAMSIM_PAIR_LDS (which closed complex64
  * launches whose row pairs read adjacent LDS partners use the pair kernel:
- * 0 none, 1 all but one-state strided launches with row runs under 1 KiB
- * whose factors are stored in natural order and but contiguous launches of
+ * 0 none, 1 all except one-state strided launches with row runs under
+ * 1 KiB whose factors are stored in natural order and contiguous launches of
  * more than 4 states with odd offsets, 2 all; default 1).  Results are
  * the same bits for every setting, and for every storage order
  * (hs_factor_storage).
