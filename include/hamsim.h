@@ -140,8 +140,8 @@ hs_status hs_build_factors(int n_qubits, int n_terms, const char *const *pauli_t
  * 3 contiguous, default 3) and HAMSIM_PAIR_LDS (which closed complex64
  * launches whose row pairs read adjacent LDS partners use the pair kernel:
  * 0 none, 1 all except one-state strided launches with row runs under
- * 1 KiB whose factors are stored in natural order and contiguous launches of
- * more than 4 states with odd offsets, 2 all; default 1).  Results are
+ * 1 KiB whose factors are stored in natural order, 2 all; odd offsets of
+ * contiguous tiles included; default 1).  Results are
  * the same bits for every setting, and for every storage order
  * (hs_factor_storage).
  * A factor whose coupling range fits no tile held in LDS (e.g. X_0 X_{n-1}

@@ -245,11 +245,8 @@ void form_runs(const Plan &P, int dtype, const PlanKey &key, EvolvePlan &ep) {
                 !permuted)
                 run.pairs = false;
             const int64_t lowmask = (int64_t(1) << run.geo.qb) - 1;
-            // odd offsets pair in contiguous tiles; by default only in launches
-            // of up to 4 states (at 8 the clamped reads cost more than the
-            // row kernel's bank conflicts)
-            const bool odd_ok = (key.pairs == 2 || (key.pairs == 1 && run.launch_batch <= 4)) &&
-                                run.geo.qb == 0 && run.geo.logW == 0 && !permuted;
+            // odd offsets pair in contiguous tiles (the pair kernel's odd-offset path)
+            const bool odd_ok = key.pairs >= 1 && run.geo.qb == 0 && run.geo.logW == 0 && !permuted;
             for (int k : run.factors)
                 for (int64_t d : P.factors[k].offs) {
                     if ((d & lowmask) != 0) run.pairs = false;

@@ -804,6 +804,9 @@ __global__ __launch_bounds__(NT) void dia_pair_kernel(TileArgs a) {
     using R = float;
     static_assert(RPT % 2 == 0, "rows come in pairs");
     static_assert(!(PERM && ODD), "odd offsets occur in contiguous tiles, which keep natural order");
+    // odd offsets with 6-8 states (one row pair per thread): pick a row's
+    // entry when used, which frees registers of the ring
+    constexpr bool SEL_AT_USE = ODD && B >= 5 && RPT == 2;
     constexpr int P = RPT / 2;
     constexpr int TS = pair_lds_rows<B, RPT, NT>();       // LDS rows per state (>= T)
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -850,8 +853,8 @@ __global__ __launch_bounds__(NT) void dia_pair_kernel(TileArgs a) {
     // 16-byte pair loads per thread, so that a workgroup of few row pairs per
     // thread (large batches: one workgroup per CU) still keeps the CU's share
     // of HBM busy while it computes.
-    // (the odd-offset path's clamped loads and selects take registers of
-    // the ring: at most 4 diagonals, one fewer than otherwise)
+    // (the odd-offset path's clamps and selects take registers of the
+    // ring: at most 4 diagonals in flight there, one fewer than otherwise)
     constexpr int PF0 = pair_pf<B, P, NT>();
     constexpr int PF = !ODD ? PF0 : (PF0 - 1 < 1 ? 1 : (PF0 - 1 > 4 ? 4 : PF0 - 1));
     const int total = a.dstart[a.nf];
@@ -881,19 +884,23 @@ __global__ __launch_bounds__(NT) void dia_pair_kernel(TileArgs a) {
         if (ODD && (dd.off & 1)) {
             // odd offset (contiguous tile, one-row windows): the pair's
             // entries e, e + 1 start at any entry.  The load stays inside
-            // the diagonal's N - |d| >= 2 entries; a pair with one row out
-            // of range takes its in-range entry from the clamped load (the
-            // other is zeroed when used).
+            // the diagonal's N - |d| >= 2 entries (clamped start el); each
+            // row's entry is taken from the loaded pair here, or when used
+            // (SEL_AT_USE).
             const int lim = dd.hi - dd.lo;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int i0 = 2 * tid + 2 * NT * p;
                 const int e = row_of(i0) + neg;
                 const int el = min(max(e, 0), lim - 2);
-                C2<R> v0, v1;
-                ld2u(cp, el, v0, v1);
-                c[p][0] = e == el ? v0 : v1;
-                c[p][1] = e + 1 == el ? v0 : v1;
+                if (SEL_AT_USE) {
+                    ld2u(cp, el, c[p][0], c[p][1]);
+                } else {
+                    C2<R> v0, v1;
+                    ld2u(cp, el, v0, v1);
+                    c[p][0] = e == el ? v0 : v1;
+                    c[p][1] = e + 1 == el ? v0 : v1;
+                }
             }
             return;
         }
@@ -913,13 +920,23 @@ __global__ __launch_bounds__(NT) void dia_pair_kernel(TileArgs a) {
             // odd); each row has its own range and closure test.  The LDS
             // read of the partner pair is clamped into the tile; in a wave
             // whose pairs all lie inside it, no selects are needed.
+            const int neg = dd.off < 0 ? dd.off : 0, lim = dd.hi - dd.lo;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 const int i0 = 2 * tid + 2 * NT * p;
                 const int r0 = row_of(i0);
                 const bool v0 = i0 < T && r0 >= dd.lo && r0 < dd.hi;
                 const bool v1 = i0 < T && r0 + 1 >= dd.lo && r0 + 1 < dd.hi;
-                const C2<R> c0 = cmask(cc[p][0], v0), c1 = cmask(cc[p][1], v1);
+                // the loaded pair starts at el = e clamped into the diagonal:
+                // a pair with one row out of range finds its in-range entry
+                // in it (the other row is zeroed)
+                C2<R> k0 = cc[p][0], k1 = cc[p][1];
+                if (SEL_AT_USE) {
+                    const int e = r0 + neg, el = min(max(e, 0), lim - 2);
+                    k0 = e == el ? cc[p][0] : cc[p][1];
+                    k1 = e + 1 == el ? cc[p][0] : cc[p][1];
+                }
+                const C2<R> c0 = cmask(k0, v0), c1 = cmask(k1, v1);
                 const int sp = i0 + mW;
                 const bool in0 = (unsigned)sp < (unsigned)T, in1 = (unsigned)(sp + 1) < (unsigned)T;
                 viol = viol || (!in0 && (c0.re != (R)0 || c0.im != (R)0)) ||

@@ -55,11 +55,10 @@ inline int tile_rows_max(int dtype, int batch, long long N, bool open = false) {
 // strided tile may have, default 256), HAMSIM_MAX_FUSE (factors per launch,
 // default 8), HAMSIM_PAIR_LDS (which closed complex64 launches whose every
 // diagonal pairs run the pair kernel: 2 all, odd offsets of contiguous tiles
-// included; 1 all except (a) one-state strided launches whose row runs are
+// included; 1 all except one-state strided launches whose row runs are
 // under 1 KiB and whose diagonals are stored in natural order --
-// translation-bound launches, where the row-by-row kernel measured faster --
-// and (b) launches of more than 4 states with odd offsets; 0 none; same
-// results; default 1),
+// translation-bound launches, where the row-by-row kernel measured faster;
+// 0 none; same results; default 1),
 // HAMSIM_XCD_SWIZZLE (which launches deal each XCD one contiguous
 // eighth of the tiles instead of every eighth tile: 0 none, 1 all, 2 strided
 // tiles only, 3 contiguous tiles only; default 3: strided launches of

@@ -4,8 +4,8 @@ In a contiguous tile a factor that flips qubit 0 has odd offsets, so the
 partners of a thread's two rows start at an odd LDS entry and the pair's
 coefficients at an odd diagonal entry.  Such closed complex64 launches run
 in the pair kernel too (8-byte aligned 16-byte loads, clamped at the ends
-of each diagonal and of the tile): with HAMSIM_PAIR_LDS=2 at every batch
-size, by default (1) up to 4 states.  Every setting must give the same
+of each diagonal and of the tile), with HAMSIM_PAIR_LDS 1 (the default) and
+2, at every batch size.  Every setting must give the same
 bits: 2 and 1 against 0 (every launch row by row).  Small states (tile =
 whole state, whole-state evolution switched off) put many row pairs at the
 clamps.
