@@ -995,8 +995,9 @@ def summarize_taylor_profiles(trace_dir, fetch_dir, write_dir, leg_output):
                   f"{alg / ms * 1e3:.0f} | {meas / alg:.3f} |")
         lo = hi
     md += ["", "The excess over the algorithmic bytes is re-reads of w by out-of-tile partner gathers: H flips "
-           "every qubit, a tile is closed over 13 of them, and far partners are no longer in L2 or the last-level "
-           "cache when they are gathered."]
+           "every qubit, a tile is closed over 13 of them, and far partners are no longer in the XCD's L2 when "
+           "they are gathered. FETCH_SIZE counts every request that leaves the L2, whether the 256 MB "
+           "last-level cache or HBM serves it."]
     path = os.path.join(OUT_DIR, "dia_tile_horner_tfim_n24_n26.md")
     with open(path, "w") as fh:
         fh.write("\n".join(md) + "\n")
